@@ -1,0 +1,198 @@
+/*
+ * blp -- batched linear programs on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the solver library (libblp.so).  It solves many independent LPs
+ * in one call, each either
+ *
+ *   simplex kind:  maximise c.x  subject to  a_i.x <= b_i  or  a_i.x >= b_i
+ *                  (one sense per row), x >= 0
+ *                  -- the standard form of Gurung & Ray, "Solving Batched
+ *                  Linear Programs on GPU and Multicore CPU", Sec. 3,
+ *                  Eqs. (1)-(3), with ">=" rows (equivalently "<=" rows with
+ *                  a negative right-hand side, Sec. 3) handled by the
+ *                  two-phase method of Sec. 3;
+ *   hyperbox kind: maximise c.x  subject to  l <= x <= u
+ *                  -- solved by the closed form of Sec. 6, Eq. (7).
+ *
+ * Simplex LPs are solved by the dense-tableau simplex iteration of Sec. 3.1
+ * (Steps 1-3 with the largest-coefficient entering rule of Sec. 4.2), one LP
+ * per GPU workgroup as in Sec. 4.1, in FP64.
+ *
+ * Conventions shared by every entry point:
+ *   - No call throws; each returns a blp_error.  Per-LP outcomes are the
+ *     BLP_OPTIMAL.. status codes written to the status array, not errors.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - Pointers documented as "device" must be HIP device memory of the
+ *     handle's device (e.g. torch.Tensor.data_ptr() of a CUDA/HIP tensor);
+ *     "host" pointers are ordinary CPU memory.
+ *   - Work is ordered on the HIP stream passed in (NULL = default stream);
+ *     the caller keeps every input alive until that stream has passed the
+ *     call.
+ */
+#ifndef BLP_H
+#define BLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLP_ABI_VERSION 1
+
+typedef struct blp_handle_s* blp_handle;
+
+/* Row sense (int8 per row).  Any nonzero value is read as ">=". */
+enum { BLP_LE = 0, BLP_GE = 1 };
+
+/* LP kind (int32 per LP). */
+enum { BLP_KIND_SIMPLEX = 0, BLP_KIND_HYPERBOX = 1 };
+
+/* Per-LP status (int32 per LP). */
+enum {
+    BLP_OPTIMAL = 0,    /* optimum found (Sec. 3.1: no positive objective-row coefficient) */
+    BLP_INFEASIBLE = 1, /* phase 1 ended above zero (Sec. 3), or a hyperbox with l_i > u_i */
+    BLP_UNBOUNDED = 2,  /* no row limits the entering variable (Sec. 3.1) */
+    BLP_ITER_LIMIT = 3, /* max_iter pivots done without reaching an optimum */
+    BLP_NUMERICAL = 4   /* non-finite input or result */
+};
+
+/* Call-level error codes. */
+typedef enum {
+    BLP_SUCCESS = 0,
+    BLP_ERR_ARG = 1,       /* invalid argument; nothing was launched */
+    BLP_ERR_NOMEM = 2,     /* device or host allocation failed */
+    BLP_ERR_HIP = 3,       /* a HIP runtime call failed (message in blp_last_error) */
+    BLP_ERR_STATE = 4,     /* call out of order (e.g. backward before any solve) */
+    BLP_ERR_TOO_LARGE = 5  /* an LP exceeds the supported size (see blp_solve_batch) */
+} blp_error;
+
+/* Scheduling modes.  They share the kernels and give identical results. */
+enum {
+    BLP_MODE_PERSISTENT = 0,      /* persistent workgroups pull LPs from size-binned device queues */
+    BLP_MODE_GRID = 1,            /* one workgroup per LP, one launch per size bin (Sec. 4.1's layout) */
+    BLP_MODE_ONE_PER_LAUNCH = 2   /* one kernel launch per LP (baseline for comparison) */
+};
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal */
+    int32_t mode;          /* BLP_MODE_* */
+    int32_t max_iter;      /* pivots per LP; 0 -> 50 (m + n) */
+    int32_t bland_after;   /* consecutive zero-step pivots before the lowest-index
+                              entering rule takes over; 0 -> max(m, n) */
+    double eps_price;      /* entering threshold on reduced costs; 0 -> 1e-9 */
+    double eps_piv;        /* minimum pivot-column entry in the ratio test; 0 -> 1e-9 */
+    double eps_feas;       /* phase-1 zero test, relative to 1 + initial infeasibility; 0 -> 1e-9 */
+    int32_t variant;       /* -1: automatic kernel choice per LP; >= 0 forces one
+                              register-tile variant (index into the library's table)
+                              and sends LPs that do not fit it to the streaming kernel;
+                              -2 forces the streaming kernel for every simplex LP */
+    int32_t workers_per_cu;/* persistent mode: workgroups per compute unit; 0 -> from occupancy */
+} blp_options;
+
+/* A batch.  LP k has m[k] rows and n[k] columns (hyperbox: m[k] = 0).
+ * Metadata arrays are HOST memory; data arrays are DEVICE memory.
+ *   A      float64, LP k's m x n matrix row-major at A + a_off[k]
+ *   b      float64, length m at b + row_off[k]
+ *   sense  int8,    length m at sense + row_off[k] (BLP_LE / BLP_GE)
+ *   c      float64, length n at c + col_off[k]
+ *   l, u   float64, length n at l/u + col_off[k] (hyperbox LPs only; may be
+ *          NULL when the batch has none)
+ * If `uniform` is nonzero, every LP has m[0], n[0], kind[0] and the offsets
+ * are the packed ones (a_off = k m n, row_off = k m, col_off = k n); the
+ * offset arrays are then ignored.  Otherwise offsets may be NULL, meaning
+ * packed in order (exclusive prefix sums of m n, m and n). */
+typedef struct {
+    int64_t count;
+    int32_t uniform;
+    int32_t reserved_;
+    const int32_t* m;
+    const int32_t* n;
+    const int32_t* kind;
+    const int64_t* a_off;
+    const int64_t* row_off;
+    const int64_t* col_off;
+    const double* A;
+    const double* b;
+    const int8_t* sense;
+    const double* c;
+    const double* l;
+    const double* u;
+} blp_batch;
+
+/* Result buffers (DEVICE memory, caller-owned).  Any NULL field makes the
+ * handle use its own buffer for that output.
+ *   status int32 [count], iters int32 [count] (pivots), obj float64 [count]
+ *   x      float64, length n at x + col_off[k]   (primal solution)
+ *   y      float64, length m at y + row_off[k]   (y_i = d obj / d b_i)
+ * obj is the optimum for BLP_OPTIMAL, the current value for BLP_ITER_LIMIT,
+ * +inf for BLP_UNBOUNDED, -inf for BLP_INFEASIBLE and NaN for BLP_NUMERICAL. */
+typedef struct {
+    int32_t* status;
+    int32_t* iters;
+    double* obj;
+    double* x;
+    double* y;
+} blp_outputs;
+
+/* Fill *opt with the defaults (device 0, persistent mode, automatic kernels). */
+blp_error blp_options_default(blp_options* opt);
+
+/* Create a handle bound to opt->device (opt may be NULL for defaults).
+ * The handle owns its device workspace and its own result buffers. */
+blp_error blp_create(blp_handle* out, const blp_options* opt);
+
+/* Solve every LP of the batch (stream-ordered; returns before the GPU is
+ * done).  Sizes: simplex LPs need 1 <= m <= 2046 and 1 <= n, with
+ * n + (number of rows whose "<=" right-hand side is negative) + 1 <= 4096;
+ * hyperbox LPs need 1 <= n.  Violations found on the host return
+ * BLP_ERR_ARG / BLP_ERR_TOO_LARGE before any launch.  `out` may be NULL.
+ * The handle remembers the batch and output pointers for blp_backward and
+ * blp_get_solution*, until the next solve. */
+blp_error blp_solve_batch(blp_handle h, const blp_batch* batch, const blp_outputs* out, void* hip_stream);
+
+/* Copy LP k's results of the last solve to HOST memory (synchronises the
+ * solve's stream).  x (length n) and y (length m) may be NULL. */
+blp_error blp_get_solution(blp_handle h, int64_t k, int32_t* status, double* obj, double* x, double* y,
+                           int32_t* iters);
+
+/* Copy all results of the last solve to HOST memory, packed like the
+ * outputs (synchronises).  Any pointer may be NULL. */
+blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, double* obj, double* x,
+                                 double* y);
+
+/* Adjoint of the last solve for loss = sum_k g[k] obj_k (an extension beyond
+ * the paper; valid at non-degenerate optima where x* and y* are unique).
+ * All pointers are DEVICE memory, packed like the batch; any output may be
+ * NULL to skip it.  Simplex LP k:  dc = g_k x*,  db = g_k y*,
+ * dA = -g_k y* x*^T (row-major at a_off[k]).  Hyperbox LP k:  dc = g_k h,
+ * dl_i = g_k min(c_i, 0),  du_i = g_k max(c_i, 0).  LPs whose status is not
+ * BLP_OPTIMAL get zero gradients. */
+blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, double* dA, double* dl,
+                       double* du, void* hip_stream);
+
+/* Number of simplex LPs of the last solve handled by each kernel class:
+ * counts[0..n_reg-1] register-tile variants, counts[n_reg] streaming
+ * kernel, counts[n_reg+1] hyperbox.  Synchronises.  *n_classes receives
+ * n_reg + 2; counts may be NULL to query that number only. */
+blp_error blp_last_bins(blp_handle h, int64_t* counts, int32_t* n_classes);
+
+/* Name and maximum tableau shape (rows incl. objective rows, columns incl.
+ * rhs) of register-tile variant v; returns BLP_ERR_ARG past the end. */
+blp_error blp_variant_info(int32_t v, char* name, int32_t name_len, int32_t* max_rows, int32_t* max_cols);
+
+/* Message of the last failed call on this handle ("" if none). */
+const char* blp_last_error(blp_handle h);
+
+/* Release the handle and its device memory (synchronises its device). */
+void blp_destroy(blp_handle h);
+
+/* BLP_ABI_VERSION of the library. */
+int32_t blp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLP_H */

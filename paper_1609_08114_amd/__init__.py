@@ -1,0 +1,279 @@
+"""Batched LP solving on one AMD MI355X: Python binding of libblp.so.
+
+The functions named ``blp_*`` are thin ctypes wrappers of the C ABI in
+``include/blp.h`` (argument marshalling only; every step of the solve runs in
+the library's HIP kernels).  PyTorch is used for device memory and streams.
+If the library has not been built, importing the binding works but any call
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblp.so")
+
+BLP_LE, BLP_GE = 0, 1
+BLP_KIND_SIMPLEX, BLP_KIND_HYPERBOX = 0, 1
+BLP_OPTIMAL, BLP_INFEASIBLE, BLP_UNBOUNDED, BLP_ITER_LIMIT, BLP_NUMERICAL = range(5)
+BLP_SUCCESS, BLP_ERR_ARG, BLP_ERR_NOMEM, BLP_ERR_HIP, BLP_ERR_STATE, BLP_ERR_TOO_LARGE = range(6)
+BLP_MODE_PERSISTENT, BLP_MODE_GRID, BLP_MODE_ONE_PER_LAUNCH = range(3)
+ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_STATE", 5: "ERR_TOO_LARGE"}
+
+# Every entry point that include/blp.h declares.
+EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
+           "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
+           "blp_variant_info"]
+
+
+class blp_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("bland_after", ctypes.c_int32), ("eps_price", ctypes.c_double), ("eps_piv", ctypes.c_double),
+                ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32)]
+
+
+class blp_batch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("uniform", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("m", ctypes.c_void_p), ("n", ctypes.c_void_p), ("kind", ctypes.c_void_p),
+                ("a_off", ctypes.c_void_p), ("row_off", ctypes.c_void_p), ("col_off", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("sense", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("l", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+class blp_outputs(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("obj", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class BlpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        P = ctypes.POINTER
+        L.blp_abi_version.restype = i32
+        L.blp_abi_version.argtypes = []
+        L.blp_options_default.argtypes = [P(blp_options)]
+        L.blp_create.argtypes = [P(vp), P(blp_options)]
+        L.blp_destroy.argtypes = [vp]
+        L.blp_destroy.restype = None
+        L.blp_last_error.argtypes = [vp]
+        L.blp_last_error.restype = ctypes.c_char_p
+        L.blp_solve_batch.argtypes = [vp, P(blp_batch), P(blp_outputs), vp]
+        L.blp_get_solution.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.blp_get_solution_batch.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.blp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.blp_last_bins.argtypes = [vp, vp, P(i32)]
+        L.blp_variant_info.argtypes = [i32, ctypes.c_char_p, i32, P(i32), P(i32)]
+        for f in EXPORTS:
+            if f not in ("blp_abi_version", "blp_destroy", "blp_last_error"):
+                getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# Same-name wrappers of the C ABI
+# ---------------------------------------------------------------------------
+def blp_abi_version() -> int:
+    return lib().blp_abi_version()
+
+
+def blp_options_default() -> blp_options:
+    o = blp_options()
+    _check(None, lib().blp_options_default(ctypes.byref(o)))
+    return o
+
+
+def blp_create(opt: blp_options | None = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(None, lib().blp_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None))
+    return h
+
+
+def blp_destroy(h) -> None:
+    lib().blp_destroy(h)
+
+
+def blp_last_error(h) -> str:
+    return (lib().blp_last_error(h) or b"").decode()
+
+
+def blp_solve_batch(h, batch: blp_batch, out: blp_outputs | None = None, stream: int | None = None) -> None:
+    _check(h, lib().blp_solve_batch(h, ctypes.byref(batch), ctypes.byref(out) if out is not None else None,
+                                    stream))
+
+
+def blp_get_solution(h, k: int, status=None, obj=None, x=None, y=None, iters=None) -> None:
+    _check(h, lib().blp_get_solution(h, k, status, obj, x, y, iters))
+
+
+def blp_get_solution_batch(h, status=None, iters=None, obj=None, x=None, y=None) -> None:
+    _check(h, lib().blp_get_solution_batch(h, status, iters, obj, x, y))
+
+
+def blp_backward(h, g, dc=None, db=None, dA=None, dl=None, du=None, stream: int | None = None) -> None:
+    _check(h, lib().blp_backward(h, g, dc, db, dA, dl, du, stream))
+
+
+def blp_last_bins(h) -> np.ndarray:
+    n = ctypes.c_int32()
+    _check(h, lib().blp_last_bins(h, None, ctypes.byref(n)))
+    out = np.zeros(n.value, np.int64)
+    _check(h, lib().blp_last_bins(h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+    return out
+
+
+def blp_variant_info(v: int):
+    name = ctypes.create_string_buffer(64)
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().blp_variant_info(v, name, 64, ctypes.byref(r), ctypes.byref(c))
+    if rc != 0:
+        return None
+    return name.value.decode(), r.value, c.value
+
+
+def variants() -> list:
+    out, v = [], 0
+    while True:
+        info = blp_variant_info(v)
+        if info is None:
+            return out
+        out.append(info)
+        v += 1
+
+
+def _check(h, rc: int) -> None:
+    if rc != 0:
+        raise BlpError(rc, blp_last_error(h) if h is not None else "")
+
+
+# ---------------------------------------------------------------------------
+# Torch-facing helpers (device memory and streams only)
+# ---------------------------------------------------------------------------
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class DeviceBatch:
+    """A packed batch whose data arrays live in device memory (torch tensors)
+    and whose metadata stays on the host (numpy), as the C ABI takes them."""
+    m: np.ndarray
+    n: np.ndarray
+    kind: np.ndarray
+    a_off: np.ndarray
+    row_off: np.ndarray
+    col_off: np.ndarray
+    A: object
+    b: object
+    sense: object
+    c: object
+    l: object
+    u: object
+    uniform: bool
+
+    @property
+    def count(self) -> int:
+        return int(self.m.shape[0]) if not self.uniform else self._count
+
+    @classmethod
+    def from_host(cls, hb, device="cuda", uniform: bool | None = None) -> "DeviceBatch":
+        import torch
+        uni = hb.uniform if uniform is None else uniform
+
+        def dev(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+
+        has_box = bool((hb.kind == 1).any())
+        db = cls(m=hb.m, n=hb.n, kind=hb.kind, a_off=hb.a_off, row_off=hb.row_off, col_off=hb.col_off,
+                 A=dev(hb.A if hb.A.size else np.zeros(1), torch.float64),
+                 b=dev(hb.b if hb.b.size else np.zeros(1), torch.float64),
+                 sense=dev(hb.sense if hb.sense.size else np.zeros(1, np.int8), torch.int8),
+                 c=dev(hb.c, torch.float64),
+                 l=dev(hb.l, torch.float64) if has_box else None,
+                 u=dev(hb.u, torch.float64) if has_box else None, uniform=uni)
+        db._count = hb.count
+        return db
+
+    def c_struct(self) -> blp_batch:
+        K = self.count
+        self._keep = [np.ascontiguousarray(a) for a in (self.m, self.n, self.kind, self.a_off, self.row_off,
+                                                       self.col_off)]
+        m, n, kind, ao, ro, co = [a.ctypes.data_as(ctypes.c_void_p) for a in self._keep]
+        return blp_batch(K, 1 if self.uniform else 0, 0, m, n, kind,
+                         None if self.uniform else ao, None if self.uniform else ro, None if self.uniform else co,
+                         _ptr(self.A), _ptr(self.b), _ptr(self.sense), _ptr(self.c), _ptr(self.l), _ptr(self.u))
+
+
+class Solver:
+    """A handle plus device result tensors.  One per host thread."""
+
+    def __init__(self, device: int = 0, mode: int = BLP_MODE_PERSISTENT, variant: int = -1, max_iter: int = 0,
+                 workers_per_cu: int = 0, bland_after: int = 0):
+        o = blp_options_default()
+        o.device, o.mode, o.variant, o.max_iter = device, mode, variant, max_iter
+        o.workers_per_cu, o.bland_after = workers_per_cu, bland_after
+        self.device = device
+        self.h = blp_create(o)
+
+    def close(self):
+        if self.h:
+            blp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, db: DeviceBatch, stream=None, outputs: dict | None = None) -> dict:
+        """Solve on `stream` (torch stream or None for the current one).
+        Returns device tensors status, iters, obj, x, y."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        K = db.count
+        tot_m = int(db.m[0]) * K if db.uniform else int((db.row_off + db.m).max(initial=0))
+        tot_n = int(db.n[0]) * K if db.uniform else int((db.col_off + db.n).max(initial=0))
+        if outputs is None:
+            outputs = {"status": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                       "iters": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                       "obj": torch.empty(max(K, 1), dtype=torch.float64, device=dev),
+                       "x": torch.empty(max(tot_n, 1), dtype=torch.float64, device=dev),
+                       "y": torch.empty(max(tot_m, 1), dtype=torch.float64, device=dev)}
+        o = blp_outputs(*[_ptr(outputs[k]) for k in ("status", "iters", "obj", "x", "y")])
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._batch = db.c_struct()
+        blp_solve_batch(self.h, self._batch, o, st.cuda_stream)
+        self._last = (db, outputs)
+        return outputs
+
+    def backward(self, g, stream=None, want=("dc", "db", "dA", "dl", "du")) -> dict:
+        import torch
+        db, _ = self._last
+        dev = g.device
+        res = {}
+        for k in want:
+            src = {"dc": db.c, "db": db.b, "dA": db.A, "dl": db.l, "du": db.u}[k]
+            res[k] = None if src is None else torch.zeros_like(src)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        blp_backward(self.h, _ptr(g), _ptr(res.get("dc")), _ptr(res.get("db")), _ptr(res.get("dA")),
+                     _ptr(res.get("dl")), _ptr(res.get("du")), st.cuda_stream)
+        return res

@@ -1,0 +1,208 @@
+// Scheduling, hyperbox and adjoint kernels.
+//
+//  - reset_bins / classify / bin_offsets / scatter: build the size-binned
+//    work lists on the device.  A simplex LP's condensed tableau has m + 2
+//    rows and n + n_art + 1 columns, where n_art (rows whose "<=" form has a
+//    negative rhs, Sec. 3) depends on the data, so the bin is chosen here
+//    and not on the host.
+//  - hyperbox: Eq. (7) of Sec. 6, one LP per thread with the paper's
+//    sequential sum (Sec. 6 uses one thread per LP for the same reason).
+//  - backward_simplex / backward_hyperbox: the adjoint of the optimum with
+//    respect to the data, from the primal and dual solutions.
+#include "aux_kernels.hpp"
+#include "blp_kernels.hpp"
+
+namespace blp {
+
+__global__ void reset_bins_kernel(int32_t* counters, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
+}
+
+// One wave per LP.  bins: 0..nreg-1 register variants, nreg streaming,
+// nreg+1 hyperbox.
+__global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable vt, int32_t* binid,
+                                                        int32_t* bin_count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < P.count; k += nwaves) {
+        int bin;
+        if (lp_kind(P, k) == 1) {
+            bin = vt.nreg + 1;
+        } else {
+            const LpRef L = lp_ref(P, k);
+            int nart = 0;
+            for (int i0 = 0; i0 < L.m; i0 += 64) {
+                const int i = i0 + lane;
+                bool art = false;
+                if (i < L.m) {
+                    const double bi = P.b[L.row_off + i];
+                    const bool ge = P.sense[L.row_off + i] != 0;
+                    art = (ge ? -bi : bi) < 0.0;
+                }
+                nart += __popcll(__ballot(art));
+            }
+            const int rows = L.m + 2, cols = L.n + nart + 1;
+            bin = vt.nreg;  // streaming kernel
+            if (vt.force >= 0) {
+                if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols) bin = vt.force;
+            } else if (vt.force == -1) {
+                long best = -1;
+                for (int v = 0; v < vt.nreg; ++v) {
+                    if (vt.rows[v] >= rows && vt.cols[v] >= cols) {
+                        const long area = (long)vt.rows[v] * vt.cols[v];
+                        if (best < 0 || area < best) {
+                            best = area;
+                            bin = v;
+                        }
+                    }
+                }
+            }
+        }
+        if (lane == 0) {
+            binid[k] = bin;
+            atomicAdd(bin_count + bin, 1);
+        }
+    }
+}
+
+__global__ void bin_offsets_kernel(const int32_t* bin_count, int32_t* bin_off, int nbins) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = 0; b < nbins; ++b) {
+            bin_off[b] = acc;
+            acc += bin_count[b];
+        }
+    }
+}
+
+__global__ void scatter_kernel(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
+                               int32_t* list) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+        const int b = binid[k];
+        const int pos = atomicAdd(bin_fill + b, 1);
+        list[bin_off[b] + pos] = (int32_t)k;
+    }
+}
+
+// Eq. (7): maximise c.x over [l, u]: x_i = l_i where c_i < 0, else u_i; the
+// value is the sequential fused multiply-add sum in increasing i.
+__global__ void hyperbox_kernel(KParams P) {
+    const int64_t len = work_len(P);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = work_item(P, q);
+        const LpRef L = lp_ref(P, k);
+        const double* c = P.c + L.col_off;
+        const double* lo = P.l + L.col_off;
+        const double* up = P.u + L.col_off;
+        double* x = P.x + L.col_off;
+        bool bad = false, empty = false;
+        double acc = 0.0;
+        for (int i = 0; i < L.n; ++i) {
+            const double ci = c[i], li = lo[i], ui = up[i];
+            bad |= !isfinite(ci) || !isfinite(li) || !isfinite(ui);
+            empty |= li > ui;
+            const double h = ci < 0.0 ? li : ui;
+            acc = __builtin_fma(ci, h, acc);
+            x[i] = h;
+        }
+        if (bad)
+            for (int i = 0; i < L.n; ++i) x[i] = __builtin_nan("");
+        P.status[k] = bad ? ST_NUMERICAL : (empty ? ST_INFEASIBLE : ST_OPTIMAL);
+        P.iters[k] = 0;
+        P.obj[k] = bad ? __builtin_nan("") : (empty ? -__builtin_inf() : acc);
+    }
+}
+
+// Adjoint for simplex LPs: dc = g x*, db = g y*, dA = -g y* x*^T.  One
+// workgroup per LP; LPs not OPTIMAL get zeros.
+__global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const double* g, double* dc, double* db,
+                                                               double* dA) {
+    for (int64_t k = blockIdx.x; k < P.count; k += gridDim.x) {
+        if (lp_kind(P, k) != 0) continue;
+        const LpRef L = lp_ref(P, k);
+        const bool ok = P.status[k] == ST_OPTIMAL;
+        const double gk = ok ? g[k] : 0.0;
+        const double* x = P.x + L.col_off;
+        const double* y = P.y + L.row_off;
+        if (dc)
+            for (int j = threadIdx.x; j < L.n; j += blockDim.x) dc[L.col_off + j] = ok ? gk * x[j] : 0.0;
+        if (db)
+            for (int i = threadIdx.x; i < L.m; i += blockDim.x) db[L.row_off + i] = ok ? gk * y[i] : 0.0;
+        if (dA) {
+            const int64_t mn = (int64_t)L.m * L.n;
+            for (int64_t e = threadIdx.x; e < mn; e += blockDim.x) {
+                const int i = (int)(e / L.n), j = (int)(e - (int64_t)i * L.n);
+                dA[L.a_off + e] = ok ? -(gk * y[i]) * x[j] : 0.0;
+            }
+        }
+    }
+}
+
+// Adjoint for hyperbox LPs: dc = g h, dl = g min(c, 0), du = g max(c, 0)
+// (with the same c_i < 0 split as the forward pass).  One LP per thread.
+__global__ void backward_hyperbox_kernel(KParams P, const double* g, double* dc, double* dl, double* du) {
+    const int64_t len = work_len(P);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = work_item(P, q);
+        const LpRef L = lp_ref(P, k);
+        const bool ok = P.status[k] == ST_OPTIMAL;
+        const double gk = ok ? g[k] : 0.0;
+        for (int i = 0; i < L.n; ++i) {
+            const double ci = P.c[L.col_off + i];
+            if (dc) dc[L.col_off + i] = ok ? gk * P.x[L.col_off + i] : 0.0;
+            if (dl) dl[L.col_off + i] = ok && ci < 0.0 ? gk * ci : 0.0;
+            if (du) du[L.col_off + i] = ok && !(ci < 0.0) ? gk * ci : 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_reset(int32_t* counters, int n, hipStream_t s) {
+    hipLaunchKernelGGL(reset_bins_kernel, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
+                           hipStream_t s) {
+    int64_t blocks = (P.count + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, vt, binid, bin_count);
+    return hipGetLastError();
+}
+hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nbins, hipStream_t s) {
+    hipLaunchKernelGGL(bin_offsets_kernel, dim3(1), dim3(64), 0, s, bin_count, bin_off, nbins);
+    return hipGetLastError();
+}
+hipError_t launch_scatter(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
+                          int32_t* list, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, binid, bin_off, bin_fill,
+                       list);
+    return hipGetLastError();
+}
+static unsigned grid_for(int64_t items, int per_block, int64_t cap) {
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s) {
+    hipLaunchKernelGGL(hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(backward_simplex_kernel, dim3(grid_for(P.count, 1, 1 << 16)), dim3(256), 0, s, P, g, dc,
+                       db, dA);
+    return hipGetLastError();
+}
+hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
+                                    double* du, hipStream_t s) {
+    hipLaunchKernelGGL(backward_hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P, g,
+                       dc, dl, du);
+    return hipGetLastError();
+}
+
+}  // namespace blp

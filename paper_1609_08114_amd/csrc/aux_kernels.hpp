@@ -1,0 +1,39 @@
+// Host-callable launchers of the solver's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "blp_kernels.hpp"
+
+namespace blp {
+
+constexpr int kMaxVariants = 24;
+
+// Register-tile variant shapes handed to the classify kernel.
+struct VariantTable {
+    int nreg;
+    int force;  // -1 automatic, -2 streaming only, >= 0 one variant
+    int rows[kMaxVariants];
+    int cols[kMaxVariants];
+};
+
+hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);
+hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
+                           hipStream_t s);
+hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nbins, hipStream_t s);
+hipError_t launch_scatter(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
+                          int32_t* list, hipStream_t s);
+hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s);
+hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,
+                                   hipStream_t s);
+hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
+                                    double* du, hipStream_t s);
+
+// Streaming kernel (simplex_gm.hip).
+hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s);
+const void* gm_kernel_ptr();
+int gm_threads();
+size_t gm_lds_bytes_host(int ld, int cols);
+
+}  // namespace blp

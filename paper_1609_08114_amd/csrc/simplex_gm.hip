@@ -1,0 +1,271 @@
+// Streaming simplex kernel for tableaux too large for a workgroup's
+// registers: one LP per workgroup, the condensed tableau in a per-workgroup
+// HBM workspace slot, column-major (element (i, j) at ws[j*ld + i]) so that
+// the column operations of Steps 2 and 3 are coalesced (Sec. 4.3).  Each
+// pivot streams the whole tableau once (read + write), which is the
+// HBM/L2-bound part; Step 1 and Step 2 run on LDS mirrors of the active
+// objective row and the rhs column exactly as in the register-tile kernel.
+//
+// Per pivot: price (LDS) -> load the entering column into LDS -> barrier ->
+// ratio test (LDS) -> gather and divide the pivot row into LDS -> barrier ->
+// stream the update over all columns (waves take columns, lanes take rows)
+// while refreshing the mirrors -> barrier.
+#include "blp_kernels.hpp"
+#include "simplex_common.hpp"
+#include "aux_kernels.hpp"
+
+namespace blp {
+
+// Dynamic LDS layout for a launch whose LPs have at most `rows` tableau rows
+// (ld, a multiple of 64) and `cols` column slots.
+struct GmLds {
+    double *d, *p, *b, *f, *sig;
+    int *colvar, *basis, *artrow, *rank;
+    unsigned char* flag;
+};
+__host__ __device__ inline size_t gm_lds_bytes(int ld, int cols) {
+    return (size_t)cols * (8 + 8 + 4) + (size_t)ld * (8 + 8 + 8 + 4 + 4 + 4 + 1) + 64;
+}
+
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
+    constexpr int NT = NW * 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ld = P.ws_ld, cg_max = P.ws_cols;
+    GmLds S;
+    S.d = reinterpret_cast<double*>(smem);
+    S.p = S.d + cg_max;
+    S.b = S.p + cg_max;
+    S.f = S.b + ld;
+    S.sig = S.f + ld;
+    S.colvar = reinterpret_cast<int*>(S.sig + ld);
+    S.basis = S.colvar + cg_max;
+    S.artrow = S.basis + ld;
+    S.rank = S.artrow + ld;
+    S.flag = reinterpret_cast<unsigned char*>(S.rank + ld);
+    __shared__ int s_k, s_nart, s_bad;
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double* const Tg = P.ws + (int64_t)blockIdx.x * P.ws_slot;
+    const int ROW_OBJ = ld - 1, ROW_W = ld - 2;
+
+    const int64_t len = work_len(P);
+    bool first = true;
+    for (;;) {
+        if (t == 0) {
+            int64_t q;
+            if (P.direct)
+                q = first ? P.direct_first + (int64_t)blockIdx.x : len;
+            else
+                q = atomicAdd(P.bin_head + P.bin, 1);
+            s_k = q < len ? (int)work_item(P, q) : -1;
+            s_bad = 0;
+        }
+        first = false;
+        __syncthreads();
+        const int k = s_k;
+        if (k < 0) break;
+
+        // ------------------------------------------------------------ load
+        const LpRef L = lp_ref(P, k);
+        const int m = L.m, n = L.n;
+        if (m > ld - 2 || n + 1 > cg_max) {  // never routed here; no LDS write past the arrays
+            write_numerical<NT>(P, L, k, t, ST_INTERNAL);
+            __syncthreads();
+            continue;
+        }
+        for (int i = t; i < ld; i += NT) {
+            S.flag[i] = 0;
+            S.b[i] = 0.0;
+        }
+        __syncthreads();
+        int bad = prep_rows<NT>(P, L, t, S.sig, S.b, S.flag);
+        __syncthreads();
+        if (t < 64) scan_art_rows(m, lane, S.flag, S.artrow, S.rank, &s_nart);
+        __syncthreads();
+        const int nart = s_nart;
+        const int C = n + nart + 1, RHS = C - 1;
+        if (m > ld - 2 || C > cg_max) {
+            write_numerical<NT>(P, L, k, t, ST_INTERNAL);
+            __syncthreads();
+            continue;
+        }
+        // constraint rows: read A row-major (coalesced), write column-major
+        for (int i = wave; i < m; i += NW) {
+            const double sg = S.sig[i];
+            for (int j = lane; j < n; j += 64) {
+                const double a = P.A[L.a_off + (int64_t)i * n + j];
+                bad |= !isfinite(a);
+                Tg[(int64_t)j * ld + i] = sg * a;
+            }
+        }
+        // the other cells, column by column
+        for (int j = wave; j < C; j += NW) {
+            const int sur_row = (j >= n && j < RHS) ? S.artrow[j - n] : -1;
+            for (int i = lane; i < ld; i += 64) {
+                if (i < m && j < n) continue;  // written above
+                double v = 0.0;
+                if (i < m) {
+                    v = j == RHS ? S.b[i] : (i == sur_row ? -1.0 : 0.0);
+                } else if (i == ROW_OBJ) {
+                    v = j < n ? P.c[L.col_off + j] : 0.0;
+                } else if (i == ROW_W && nart > 0) {
+                    double acc = 0.0;
+                    if (j < n) {
+                        for (int q = 0; q < nart; ++q) {
+                            const int ii = S.artrow[q];
+                            acc = acc + S.sig[ii] * P.A[L.a_off + (int64_t)ii * n + j];
+                        }
+                    } else if (j < RHS) {
+                        acc = -1.0;
+                    } else {
+                        for (int q = 0; q < nart; ++q) acc = acc + S.b[S.artrow[q]];
+                    }
+                    v = acc;
+                }
+                Tg[(int64_t)j * ld + i] = v;
+            }
+        }
+        if (bad) atomicOr(&s_bad, 1);
+        for (int j = t; j < C; j += NT) S.colvar[j] = j < n ? j : (j < RHS ? n + S.artrow[j - n] : ID_NONE);
+        for (int i = t; i < m; i += NT) S.basis[i] = (S.flag[i] & RF_ART) ? n + m + i : n + i;
+        __syncthreads();
+        if (s_bad) {
+            write_numerical<NT>(P, L, k, t, ST_NUMERICAL);
+            __syncthreads();
+            continue;
+        }
+        int phase = nart > 0 ? 1 : 2;
+        auto mirror_row = [&](int row) {
+            for (int j = t; j < C; j += NT) S.d[j] = Tg[(int64_t)j * ld + row];
+        };
+        mirror_row(phase == 1 ? ROW_W : ROW_OBJ);
+        for (int i = t; i < ld; i += NT) S.b[i] = Tg[(int64_t)RHS * ld + i];
+        __syncthreads();
+        const double w0 = S.b[ROW_W];
+        const int max_iter = P.max_iter > 0 ? P.max_iter : 50 * (m + n);
+        const int bland_after = P.bland_after > 0 ? P.bland_after : (m > n ? m : n);
+        const int id_lim = n + m;
+        int iters = 0, degen = 0, st = -1;
+
+        // ------------------------------------------------------ pivot loop
+        int mode = phase, drive_r = 0;
+        for (;;) {
+            int e_id, e, l = -1;
+            double rmin = 1.0;
+            if (mode == 3) {
+                int r0 = -1;
+                for (; drive_r < m; ++drive_r)
+                    if (S.basis[drive_r] >= id_lim && !(S.flag[drive_r] & RF_DEAD)) {
+                        r0 = drive_r;
+                        break;
+                    }
+                if (r0 < 0) {
+                    mode = phase = 2;
+                    degen = 0;
+                    mirror_row(ROW_OBJ);
+                    __syncthreads();
+                    continue;
+                }
+                ++drive_r;
+                for (int j = t; j < C; j += NT) S.p[j] = Tg[(int64_t)j * ld + r0];
+                __syncthreads();
+                double bk = -__builtin_inf();
+                int bid = ID_NONE, bpos = -1;
+                for (int j = lane; j < RHS; j += 64) {
+                    const int v = S.colvar[j];
+                    if (v < id_lim && fabs(S.p[j]) > P.eps_piv && key_before(0.0, v, bk, bid)) {
+                        bk = 0.0;
+                        bid = v;
+                        bpos = j;
+                    }
+                }
+                wave_argmax(bk, bid, bpos);
+                __syncthreads();
+                if (bid == ID_NONE) {
+                    if (t == 0) S.flag[r0] |= RF_DEAD;
+                    __syncthreads();
+                    continue;
+                }
+                l = r0;
+                e = bpos;
+                e_id = bid;
+            } else {
+                price(RHS, lane, id_lim, P.eps_price, degen >= bland_after, S.d, S.colvar, e_id, e);
+                if (e_id == ID_NONE) {
+                    if (mode == 2) {
+                        st = ST_OPTIMAL;
+                        break;
+                    }
+                    if (S.b[ROW_W] > P.eps_feas * (1.0 + w0)) {
+                        st = ST_INFEASIBLE;
+                        break;
+                    }
+                    mode = 3;
+                    drive_r = 0;
+                    continue;
+                }
+                if (iters >= max_iter) {
+                    st = ST_ITER_LIMIT;
+                    break;
+                }
+            }
+            // entering column -> LDS
+            const double* colE = Tg + (int64_t)e * ld;
+            for (int i = t; i < ld; i += NT) S.f[i] = colE[i];
+            __syncthreads();
+            if (mode != 3) {
+                l = ratio_test(m, lane, P.eps_piv, S.f, S.b, S.basis, S.flag, rmin);
+                if (l < 0) {
+                    st = mode == 2 ? ST_UNBOUNDED : ST_NUMERICAL;
+                    break;
+                }
+            }
+            // Step 3: NewPivotRow = OldPivotRow / PE (the entering slot takes
+            // the leaving variable's column, whose pivot-row entry is 1 / PE)
+            const double pe = S.f[l];
+            for (int j = t; j < C; j += NT) S.p[j] = (j == e ? 1.0 : Tg[(int64_t)j * ld + l]) / pe;
+            __syncthreads();
+            const int act = phase == 1 ? ROW_W : ROW_OBJ;
+            for (int j = wave; j < C; j += NW) {
+                double* col = Tg + (int64_t)j * ld;
+                const double pj = S.p[j];
+                const bool je = j == e;
+                for (int i = lane; i < ld; i += 64) {
+                    const double old = je ? 0.0 : col[i];
+                    double v = __builtin_fma(-S.f[i], pj, old);
+                    v = i == l ? pj : v;
+                    col[i] = v;
+                    if (i == act) S.d[j] = v;
+                    if (j == RHS) S.b[i] = v;
+                }
+            }
+            if (t == 0) {
+                S.colvar[e] = S.basis[l];
+                S.basis[l] = e_id;
+            }
+            __syncthreads();
+            ++iters;
+            if (mode != 3) degen = rmin == 0.0 ? degen + 1 : 0;
+        }
+
+        // ------------------------------------------------------ extraction
+        mirror_row(ROW_OBJ);
+        __syncthreads();
+        write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, RHS, S.d, S.b, S.colvar, S.basis, S.flag, S.p, S.f);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL((simplex_gm_kernel<8>), dim3(grid), dim3(512), lds_bytes, s, P);
+    return hipGetLastError();
+}
+const void* gm_kernel_ptr() { return reinterpret_cast<const void*>(&simplex_gm_kernel<8>); }
+int gm_threads() { return 512; }
+
+}  // namespace blp
+
+namespace blp {
+size_t gm_lds_bytes_host(int ld, int cols) { return gm_lds_bytes(ld, cols); }
+}  // namespace blp

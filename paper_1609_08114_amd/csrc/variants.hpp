@@ -1,0 +1,36 @@
+// Table of register-tile kernel variants.  Each entry fixes the thread grid
+// of simplex_reg_kernel:
+//   (name, waves, TC threads per tableau row, CT columns per thread, target
+//    waves per SIMD)
+// giving a maximum tableau of 64*waves/TC rows by TC*CT columns (objective
+// rows and the rhs column included).  The scheduler sends each LP
+// to the fitting variant of smallest area.
+#pragma once
+
+#include "blp_kernels.hpp"
+
+namespace blp {
+
+struct RegVariant {
+    const char* name;
+    int threads;
+    int max_rows;
+    int max_cols;
+    hipError_t (*launch)(const KParams&, int grid, hipStream_t);
+    const void* (*kernel)();
+};
+
+// Host-side table of the compiled variants.
+const RegVariant* reg_variants(int* count);
+
+// clang-format off
+#define BLP_REG_VARIANT_LIST                                  \
+    BLP_REG_VARIANT("w1_r8_c8",      1, 8,   1, 8)           \
+    BLP_REG_VARIANT("w1_r16_c16",    1, 4,   4, 4)           \
+    BLP_REG_VARIANT("w1_r32_c32",    1, 2,  16, 2)           \
+    BLP_REG_VARIANT("w2_r64_c64",    2, 2,  32, 1)           \
+    BLP_REG_VARIANT("w4_r128_c112",  4, 2,  56, 1)           \
+    BLP_REG_VARIANT("w8_r128_c128",  8, 4,  32, 2)
+// clang-format on
+
+}  // namespace blp
