@@ -1,0 +1,226 @@
+#!/usr/bin/env python
+"""Throughput of the batched LP solver on one MI355X.
+
+Workload (one step): solve 50,000 type-1 LPs with m = n = 100 (A~U(1,10),
+b~U(10,100), c~U(1,10), seed 1002), inputs resident in HBM, persistent
+size-binned kernels.  Prints ONE JSON line with LPs/s, the same batch's
+one-LP-per-launch rate on a sample, LPs/s of the other workload classes,
+the roofline of the dominant kernel (HIP events recorded by the library on
+the solve's stream) and the CPU oracle's rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_simplex_reg_100x100.json")
+KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_common.hpp",
+                  "paper_1609_08114_amd/csrc/blp_kernels.hpp", "paper_1609_08114_amd/csrc/variants.hpp"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_solver(blp, torch, db, steps, warmup, **kw):
+    """Warm up, then time `steps` solves; returns (ms per step, per-class
+    kernel ms averaged over the timed steps, last outputs, bins)."""
+    s = blp.Solver(profile=True, **kw)
+    stream = torch.cuda.Stream()
+    out = None
+    for _ in range(warmup):
+        out = s.solve(db, stream=stream)
+    torch.cuda.synchronize()
+    kms = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = s.solve(db, stream=stream)
+        k = blp.blp_last_kernel_ms(s.h)  # synchronises the stream
+        kms = k if kms is None else kms + k
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bins = blp.blp_last_bins(s.h)
+    s.close()
+    return (t1 - t0) * 1e3 / steps, kms / steps, out, bins
+
+
+def rate_one_per_launch(blp, torch, lpgen, cfg, ids, **kw):
+    hb = lpgen.config(cfg, ids) if not isinstance(cfg, tuple) else lpgen.config(cfg[0], ids, part=cfg[1])
+    db = blp.DeviceBatch.from_host(hb)
+    ms, _, out, _ = time_solver(blp, torch, db, 1, 1, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
+    return hb.count / (ms / 1e3), ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=50_000)
+    ap.add_argument("--one-per-launch-sample", type=int, default=2_000)
+    ap.add_argument("--cpu-sample", type=int, default=20_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-classes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch shards across GPUs "
+              "with no exchange, so run one process per GPU instead.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lpgen
+    import paper_1609_08114_amd as blp
+    assert torch.cuda.is_available(), "needs a GPU"
+
+    # ------------------------------------------------------------ main line
+    K = args.batch
+    log(f"generating {K} type-1 LPs 100x100")
+    t = time.perf_counter()
+    hb = lpgen.config(2, range(K))
+    log(f"generated in {time.perf_counter() - t:.1f}s; copying to HBM")
+    db = blp.DeviceBatch.from_host(hb)
+    torch.cuda.synchronize()
+    log("timing persistent mode")
+    ms, kms, out, bins = time_solver(blp, torch, db, args.steps, args.warmup)
+    status = out["status"][:K].cpu().numpy()
+    iters = out["iters"][:K].cpu().numpy().astype(np.int64)
+    obj = out["obj"][:K].cpu().numpy()
+    value = K / (ms / 1e3)
+    log(f"persistent: {ms:.3f} ms/step, {value:,.0f} LPs/s, statuses {np.bincount(status, minlength=5)}")
+
+    # dominant kernel (largest device time) and its roofline
+    names = [v[0] for v in blp.variants()] + ["streaming", "hyperbox", "binning"]
+    dom = int(np.argmax(kms))
+    dom_ms = float(kms[dom])
+    m = n = 100
+    # condensed tableau of a type-1 LP: (m + 1) rows x (n + 1) columns; one
+    # pivot = one FMA per entry
+    flops = float(iters.sum()) * 2.0 * (m + 1) * (n + 1)
+    achieved = flops / (dom_ms / 1e3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("kernel_source_hash") == kernel_source_hash() and tf.get("batch") == K:
+            traffic = tf.get("bytes_per_launch")
+    input_bytes = K * 8.0 * (m * n + m + n) + K * (m + 2 * 4 + 8 + 8 * (m + n))
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                "kernel": names[dom], "kernel_ms": round(dom_ms, 4),
+                "algorithmic_flops": flops, "pivots": int(iters.sum()),
+                "hbm_input_bytes": input_bytes,
+                "hbm_frac_of_input_read": round(input_bytes / (dom_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+    # ------------------------------------------------- one LP per launch
+    S = min(args.one_per_launch_sample, K)
+    log(f"one-LP-per-launch on the first {S} LPs")
+    sub = blp.DeviceBatch.from_host(lpgen.config(2, range(S)))
+    ms1, _, out1, _ = time_solver(blp, torch, sub, 1, 1, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
+    rate1 = S / (ms1 / 1e3)
+    assert np.array_equal(out1["obj"][:S].cpu().numpy().view(np.int64), obj[:S].view(np.int64))
+    log(f"one-per-launch: {rate1:,.0f} LPs/s")
+
+    # -------------------------------------------------- other size classes
+    per_class = {}
+    if not args.no_classes:
+        per_class = bench_classes(blp, torch, lpgen)
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        C = min(args.cpu_sample, K)
+        ids = np.arange(C)
+        sample = lpgen.config(2, ids)
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"CPU oracle on {C} LPs, {cores} threads")
+        t = time.perf_counter()
+        ref = oracle.solve_batch(sample)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(C / dt, 1), "unit": "LPs/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {C} LPs of the 50,000-LP batch (type 1, m=n=100), OpenMP one LP per thread",
+               "seconds": round(dt, 3)}
+        rel = np.abs(obj[:C] - ref["obj"]) / np.maximum(1.0, np.abs(ref["obj"]))
+        parity = {"checked": C, "status_mismatch": int((status[:C] != ref["status"]).sum()),
+                  "max_obj_relerr": float(rel.max()),
+                  "iters_mismatch": int((iters[:C] != ref["iters"]).sum()),
+                  "obj_bit_identical": int((obj[:C].view(np.int64) == ref["obj"].view(np.int64)).sum())}
+        log(f"oracle: {cpu['value']:,.0f} LPs/s; parity {parity}")
+
+    line = {
+        "metric": "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr<=1e-9",
+        "value": round(value, 1), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "type-1 dense LPs, m=n=100 (tableau 101x101 condensed, 101x201 full), "
+                               "A~U(1,10) b~U(10,100) c~U(1,10), seed 1002",
+                   "batch": K, "m": 100, "n": 100, "mode": "persistent"},
+        "one_per_launch": {"value": round(rate1, 1), "unit": "LPs/s", "sample": f"first {S} LPs",
+                           "speedup_persistent": round(value / rate1, 2)},
+        "statuses": np.bincount(status, minlength=5).tolist(),
+        "pivots_per_lp": round(float(iters.mean()), 3),
+        "bins": {names[i]: int(bins[i]) for i in range(len(bins)) if bins[i]},
+        "kernel_ms": {names[i]: round(float(kms[i]), 4) for i in range(len(kms)) if kms[i] > 0},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "per_class": per_class,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_classes(blp, torch, lpgen) -> dict:
+    """LPs/s of the other workload shapes, persistent vs one per launch, on
+    bounded samples (named in each entry)."""
+    res = {}
+    plan = [
+        ("type1_5x5", 1, None, 1000, 1000),
+        ("type2_200x200", 3, None, 1000, 50),
+        ("mixed_5..300", 4, None, 4000, 200),
+        ("hyperbox_n5", 5, "box5", 1_000_000, 0),
+        ("hyperbox_n28", 5, "box28", 1_000_000, 0),
+        ("type1_20..150", 5, "simplex", 4000, 200),
+    ]
+    for name, cfg, part, n_batch, n_single in plan:
+        log(f"class {name}: {n_batch} LPs")
+        hb = lpgen.config(cfg, range(n_batch), part=part) if part else lpgen.config(cfg, range(n_batch))
+        db = blp.DeviceBatch.from_host(hb)
+        ms, _, out, _ = time_solver(blp, torch, db, 3, 1)
+        st = np.bincount(out["status"][:n_batch].cpu().numpy(), minlength=5).tolist()
+        entry = {"lps": n_batch, "persistent_lps_per_s": round(n_batch / (ms / 1e3), 1), "ms": round(ms, 3),
+                 "statuses": st}
+        if n_single:
+            sub = lpgen.config(cfg, range(n_single), part=part) if part else lpgen.config(cfg, range(n_single))
+            sdb = blp.DeviceBatch.from_host(sub)
+            ms1, _, _, _ = time_solver(blp, torch, sdb, 1, 0, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
+            entry["one_per_launch_lps_per_s"] = round(n_single / (ms1 / 1e3), 1)
+            entry["one_per_launch_sample"] = n_single
+            entry["speedup"] = round(entry["persistent_lps_per_s"] / entry["one_per_launch_lps_per_s"], 2)
+        res[name] = entry
+        log(f"  {entry}")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,9 @@ typedef struct {
                               and sends LPs that do not fit it to the streaming kernel;
                               -2 forces the streaming kernel for every simplex LP */
     int32_t workers_per_cu;/* persistent mode: workgroups per compute unit; 0 -> from occupancy */
+    int32_t profile;       /* nonzero: record HIP events around each kernel class (blp_last_kernel_ms) */
+    int32_t graph;         /* nonzero (persistent mode): capture the launch sequence into a hipGraph
+                              per batch signature and replay it when the same batch recurs */
 } blp_options;
 
 /* A batch.  LP k has m[k] rows and n[k] columns (hyperbox: m[k] = 0).
@@ -177,6 +180,33 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
  * kernel, counts[n_reg+1] hyperbox.  Synchronises.  *n_classes receives
  * n_reg + 2; counts may be NULL to query that number only. */
 blp_error blp_last_bins(blp_handle h, int64_t* counts, int32_t* n_classes);
+
+/* Device time of each kernel class in the last solve, from HIP events
+ * recorded on the solve's stream around that class's launches (only when
+ * the handle was created with opt->profile != 0; otherwise all zero).
+ * ms[0..n_reg-1] register-tile variants, ms[n_reg] streaming kernel,
+ * ms[n_reg+1] hyperbox kernel, ms[n_reg+2] work-list construction.
+ * Synchronises.  *n_entries receives n_reg + 3; ms may be NULL. */
+blp_error blp_last_kernel_ms(blp_handle h, double* ms, int32_t* n_entries);
+
+/* Autotuner.  Classifies `batch` (DEVICE data as for blp_solve_batch), then
+ * for every size bin that received LPs times each kernel variant able to
+ * hold that bin's LPs (register-tile variants of equal or larger shape, and
+ * the streaming kernel) on up to `sample` of its LPs, and remaps the bin to
+ * the fastest.  The remap applies to later solves on this handle.  Results
+ * never depend on it: every variant computes bit-identical outputs.  If
+ * cache_path is non-NULL the table is also written there as JSON.
+ * Synchronises the stream. */
+blp_error blp_autotune(blp_handle h, const blp_batch* batch, int32_t sample, const char* cache_path,
+                       void* hip_stream);
+
+/* Load a table written by blp_autotune (same device name and CU count). */
+blp_error blp_load_tuning(blp_handle h, const char* cache_path);
+
+/* Current remap: remap[v] is the variant used for LPs whose best-fitting
+ * variant is v (v in [0, n_reg)); a value n_reg means the streaming kernel.
+ * *n_reg receives the number of register-tile variants. */
+blp_error blp_tuning(blp_handle h, int32_t* remap, int32_t* n_reg);
 
 /* Name and maximum tableau shape (rows incl. objective rows, columns incl.
  * rhs) of register-tile variant v; returns BLP_ERR_ARG past the end. */

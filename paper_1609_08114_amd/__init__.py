@@ -27,13 +27,14 @@ ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR
 # Every entry point that include/blp.h declares.
 EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
-           "blp_variant_info"]
+           "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning"]
 
 
 class blp_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("bland_after", ctypes.c_int32), ("eps_price", ctypes.c_double), ("eps_piv", ctypes.c_double),
-                ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32)]
+                ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class blp_batch(ctypes.Structure):
@@ -81,6 +82,10 @@ def lib() -> ctypes.CDLL:
         L.blp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.blp_last_bins.argtypes = [vp, vp, P(i32)]
         L.blp_variant_info.argtypes = [i32, ctypes.c_char_p, i32, P(i32), P(i32)]
+        L.blp_last_kernel_ms.argtypes = [vp, vp, P(i32)]
+        L.blp_autotune.argtypes = [vp, P(blp_batch), i32, ctypes.c_char_p, vp]
+        L.blp_load_tuning.argtypes = [vp, ctypes.c_char_p]
+        L.blp_tuning.argtypes = [vp, vp, P(i32)]
         for f in EXPORTS:
             if f not in ("blp_abi_version", "blp_destroy", "blp_last_error"):
                 getattr(L, f).restype = ctypes.c_int
@@ -137,6 +142,32 @@ def blp_last_bins(h) -> np.ndarray:
     _check(h, lib().blp_last_bins(h, None, ctypes.byref(n)))
     out = np.zeros(n.value, np.int64)
     _check(h, lib().blp_last_bins(h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+    return out
+
+
+def blp_last_kernel_ms(h) -> np.ndarray:
+    n = ctypes.c_int32()
+    _check(h, lib().blp_last_kernel_ms(h, None, ctypes.byref(n)))
+    out = np.zeros(n.value, np.float64)
+    _check(h, lib().blp_last_kernel_ms(h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+    return out
+
+
+def blp_autotune(h, batch: blp_batch, sample: int = 512, cache_path: str | None = None,
+                 stream: int | None = None) -> None:
+    _check(h, lib().blp_autotune(h, ctypes.byref(batch), sample,
+                                 cache_path.encode() if cache_path else None, stream))
+
+
+def blp_load_tuning(h, cache_path: str) -> None:
+    _check(h, lib().blp_load_tuning(h, cache_path.encode()))
+
+
+def blp_tuning(h) -> np.ndarray:
+    n = ctypes.c_int32()
+    _check(h, lib().blp_tuning(h, None, ctypes.byref(n)))
+    out = np.zeros(n.value, np.int32)
+    _check(h, lib().blp_tuning(h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
     return out
 
 
@@ -226,10 +257,11 @@ class Solver:
     """A handle plus device result tensors.  One per host thread."""
 
     def __init__(self, device: int = 0, mode: int = BLP_MODE_PERSISTENT, variant: int = -1, max_iter: int = 0,
-                 workers_per_cu: int = 0, bland_after: int = 0):
+                 workers_per_cu: int = 0, bland_after: int = 0, profile: bool = False, graph: bool = False):
         o = blp_options_default()
         o.device, o.mode, o.variant, o.max_iter = device, mode, variant, max_iter
-        o.workers_per_cu, o.bland_after = workers_per_cu, bland_after
+        o.workers_per_cu, o.bland_after, o.profile = workers_per_cu, bland_after, 1 if profile else 0
+        o.graph = 1 if graph else 0
         self.device = device
         self.h = blp_create(o)
 
@@ -264,6 +296,12 @@ class Solver:
         blp_solve_batch(self.h, self._batch, o, st.cuda_stream)
         self._last = (db, outputs)
         return outputs
+
+    def autotune(self, db: DeviceBatch, sample: int = 512, cache_path: str | None = None, stream=None) -> None:
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.device))
+        self._tune_batch = db.c_struct()
+        blp_autotune(self.h, self._tune_batch, sample, cache_path, st.cuda_stream)
 
     def backward(self, g, stream=None, want=("dc", "db", "dA", "dl", "du")) -> dict:
         import torch

@@ -18,10 +18,15 @@ __global__ void reset_bins_kernel(int32_t* counters, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
 }
 
-// One wave per LP.  bins: 0..nreg-1 register variants, nreg streaming,
-// nreg+1 hyperbox.
+// One wave per LP; per-block bin histogram in LDS, flushed with one atomic
+// per (block, bin) so that a uniform batch does not serialise on one
+// counter.  bins: 0..nreg-1 register variants, nreg streaming, nreg+1
+// hyperbox.
 __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable vt, int32_t* binid,
                                                         int32_t* bin_count) {
+    __shared__ int hist[kMaxVariants + 2];
+    for (int b = threadIdx.x; b < vt.nreg + 2; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < P.count; k += nwaves) {
@@ -56,13 +61,17 @@ __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable v
                         }
                     }
                 }
+                if (bin < vt.nreg) bin = vt.remap[bin];
             }
         }
         if (lane == 0) {
             binid[k] = bin;
-            atomicAdd(bin_count + bin, 1);
+            atomicAdd(&hist[bin], 1);
         }
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < vt.nreg + 2; b += blockDim.x)
+        if (hist[b]) atomicAdd(bin_count + b, hist[b]);
 }
 
 __global__ void bin_offsets_kernel(const int32_t* bin_count, int32_t* bin_off, int nbins) {
@@ -75,12 +84,29 @@ __global__ void bin_offsets_kernel(const int32_t* bin_count, int32_t* bin_off, i
     }
 }
 
-__global__ void scatter_kernel(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
-                               int32_t* list) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
-        const int b = binid[k];
-        const int pos = atomicAdd(bin_fill + b, 1);
-        list[bin_off[b] + pos] = (int32_t)k;
+// Each block takes a contiguous chunk of LPs, counts its bins in LDS,
+// reserves one range per bin with a single atomic, then writes its entries
+// (in LP order within the block).
+__global__ void __launch_bounds__(256) scatter_kernel(int64_t count, int nbins, const int32_t* binid,
+                                                      const int32_t* bin_off, int32_t* bin_fill, int32_t* list) {
+    __shared__ int hist[kMaxVariants + 2], base[kMaxVariants + 2];
+    const int64_t chunk = 2048;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < count; c0 += (int64_t)gridDim.x * chunk) {
+        const int64_t c1 = c0 + chunk < count ? c0 + chunk : count;
+        for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        for (int64_t k = c0 + threadIdx.x; k < c1; k += blockDim.x) atomicAdd(&hist[binid[k]], 1);
+        __syncthreads();
+        for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+            base[b] = hist[b] ? bin_off[b] + atomicAdd(bin_fill + b, hist[b]) : 0;
+            hist[b] = 0;
+        }
+        __syncthreads();
+        for (int64_t k = c0 + threadIdx.x; k < c1; k += blockDim.x) {
+            const int b = binid[k];
+            list[base[b] + atomicAdd(&hist[b], 1)] = (int32_t)k;
+        }
+        __syncthreads();
     }
 }
 
@@ -163,8 +189,8 @@ hipError_t launch_reset(int32_t* counters, int n, hipStream_t s) {
 }
 hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
                            hipStream_t s) {
-    int64_t blocks = (P.count + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
+    int64_t blocks = (P.count + 63) / 64;  // 16 LPs per wave
+    if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, vt, binid, bin_count);
     return hipGetLastError();
@@ -173,13 +199,13 @@ hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nb
     hipLaunchKernelGGL(bin_offsets_kernel, dim3(1), dim3(64), 0, s, bin_count, bin_off, nbins);
     return hipGetLastError();
 }
-hipError_t launch_scatter(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
+hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
                           int32_t* list, hipStream_t s) {
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    int64_t blocks = (count + 2047) / 2048;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, binid, bin_off, bin_fill,
-                       list);
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, nbins, binid, bin_off,
+                       bin_fill, list);
     return hipGetLastError();
 }
 static unsigned grid_for(int64_t items, int per_block, int64_t cap) {

@@ -16,13 +16,14 @@ struct VariantTable {
     int force;  // -1 automatic, -2 streaming only, >= 0 one variant
     int rows[kMaxVariants];
     int cols[kMaxVariants];
+    int remap[kMaxVariants];  // autotuned replacement of each variant (nreg = streaming)
 };
 
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);
 hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
                            hipStream_t s);
 hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nbins, hipStream_t s);
-hipError_t launch_scatter(int64_t count, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
+hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
                           int32_t* list, hipStream_t s);
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s);
 hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,

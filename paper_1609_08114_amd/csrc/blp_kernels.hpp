@@ -56,7 +56,32 @@ struct KParams {
     int64_t ws_slot;
     int32_t ws_ld;   // leading dimension (rows, multiple of 64)
     int32_t ws_cols; // columns available per slot
+    // phase cycle counters (only with -DBLP_PHASE_TIMERS; NULL otherwise)
+    unsigned long long* timers;
 };
+
+// Optional in-kernel phase timers (s_memtime cycles of wave 0, summed over
+// workgroups): build with -DBLP_PHASE_TIMERS.  Slots: 0 load, 1 price,
+// 2 entering-column publish, 3 ratio test, 4 pivot update, 5 extraction,
+// 6 pivots, 7 LPs.
+enum { TM_LOAD = 0, TM_PRICE, TM_PUBCOL, TM_RATIO, TM_PIVOT, TM_EXTRACT, TM_PIVOTS, TM_LPS, TM_SLOTS };
+#ifdef BLP_PHASE_TIMERS
+#define BLP_TDECL unsigned long long tm_acc_[TM_SLOTS] = {}
+#define BLP_T(v) const unsigned long long v = __builtin_readcyclecounter()
+#define BLP_TACC(slot, a, b) (tm_acc_[slot] += (b) - (a))
+#define BLP_TCOUNT(slot, n) (tm_acc_[slot] += (n))
+#define BLP_TFLUSH()                                                                  \
+    do {                                                                              \
+        if (threadIdx.x == 0 && P.timers)                                             \
+            for (int s_ = 0; s_ < TM_SLOTS; ++s_) atomicAdd(P.timers + s_, tm_acc_[s_]); \
+    } while (0)
+#else
+#define BLP_TDECL
+#define BLP_T(v)
+#define BLP_TACC(slot, a, b)
+#define BLP_TCOUNT(slot, n)
+#define BLP_TFLUSH()
+#endif
 
 struct LpRef {
     int32_t m, n;
@@ -95,59 +120,72 @@ __device__ __forceinline__ int64_t work_item(const KParams& P, int64_t q) {
 // Wave-wide arg-max of (key, id) pairs under the total order
 //   a before b  <=>  a.key > b.key, or a.key == b.key and a.id < b.id
 // carrying a payload.  Ids are unique within a reduction, so every lane ends
-// with the same winner whatever the combination order.  Within each 16-lane
-// row the exchange uses DPP (quad permutes, then row rotations by 4 and 8);
-// across rows, lane shuffles by 16 and 32.
+// with the same winner whatever the combination order.  The id (< 2^15) and
+// the payload position (< 2^16) travel packed in one dword, id in the high
+// half, so comparing packed values orders by id.  Within each 16-lane row
+// the exchange uses DPP (quad permutes, then row rotations by 4 and 8);
+// across rows, gfx950's permlane16/permlane32 swaps (lane ^ 16, lane ^ 32).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool key_before(double ak, int aid, double bk, int bid) {
     return ak > bk || (ak == bk && aid < bid);
 }
 
+constexpr int PACK_NONE = 0x7fffffff;
+__device__ __forceinline__ int pack_id(int id, int pos) { return id == ID_NONE ? PACK_NONE : (id << 16) | pos; }
+__device__ __forceinline__ int unpack_id(int p) { return p == PACK_NONE ? ID_NONE : (p >> 16); }
+__device__ __forceinline__ int unpack_pos(int p) { return p == PACK_NONE ? -1 : (p & 0xffff); }
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
     return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = dpp_i32<CTRL>(lo);
-    hi = dpp_i32<CTRL>(hi);
-    return __hiloint2double(hi, lo);
+
+// Value of lane ^ 16 / lane ^ 32 (lane layout of the swaps checked on the
+// device: the first result holds the lower source half in the upper lanes).
+__device__ __forceinline__ int xor16_i32(int v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ int xor32_i32(int v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
 }
 
 template <int CTRL>
-__device__ __forceinline__ void argmax_dpp_step(double& k, int& id, int& pos) {
-    double ok = dpp_f64<CTRL>(k);
-    int oid = dpp_i32<CTRL>(id);
-    int opos = dpp_i32<CTRL>(pos);
-    if (key_before(ok, oid, k, id)) {
+__device__ __forceinline__ void argmax_step_dpp(double& k, int& pk) {
+    const int lo = dpp_i32<CTRL>(__double2loint(k));
+    const int hi = dpp_i32<CTRL>(__double2hiint(k));
+    const double ok = __hiloint2double(hi, lo);
+    const int opk = dpp_i32<CTRL>(pk);
+    if (ok > k || (ok == k && opk < pk)) {
         k = ok;
-        id = oid;
-        pos = opos;
+        pk = opk;
+    }
+}
+template <int X>
+__device__ __forceinline__ void argmax_step_swap(double& k, int& pk) {
+    const int lo = X == 16 ? xor16_i32(__double2loint(k)) : xor32_i32(__double2loint(k));
+    const int hi = X == 16 ? xor16_i32(__double2hiint(k)) : xor32_i32(__double2hiint(k));
+    const double ok = __hiloint2double(hi, lo);
+    const int opk = X == 16 ? xor16_i32(pk) : xor32_i32(pk);
+    if (ok > k || (ok == k && opk < pk)) {
+        k = ok;
+        pk = opk;
     }
 }
 
-__device__ __forceinline__ void argmax_shfl_step(double& k, int& id, int& pos, int mask) {
-    double ok = __shfl_xor(k, mask, 64);
-    int oid = __shfl_xor(id, mask, 64);
-    int opos = __shfl_xor(pos, mask, 64);
-    if (key_before(ok, oid, k, id)) {
-        k = ok;
-        id = oid;
-        pos = opos;
-    }
-}
-
-// All 64 lanes must be active.
+// All 64 lanes must be active.  On return id/pos are wave-uniform.
 __device__ __forceinline__ void wave_argmax(double& k, int& id, int& pos) {
-    argmax_dpp_step<0xB1>(k, id, pos);   // quad_perm [1,0,3,2]: lane ^ 1
-    argmax_dpp_step<0x4E>(k, id, pos);   // quad_perm [2,3,0,1]: lane ^ 2
-    argmax_dpp_step<0x124>(k, id, pos);  // row_ror:4
-    argmax_dpp_step<0x128>(k, id, pos);  // row_ror:8
-    argmax_shfl_step(k, id, pos, 16);
-    argmax_shfl_step(k, id, pos, 32);
-    id = __builtin_amdgcn_readfirstlane(id);
-    pos = __builtin_amdgcn_readfirstlane(pos);
+    int pk = pack_id(id, pos);
+    argmax_step_dpp<0xB1>(k, pk);   // quad_perm [1,0,3,2]: lane ^ 1
+    argmax_step_dpp<0x4E>(k, pk);   // quad_perm [2,3,0,1]: lane ^ 2
+    argmax_step_dpp<0x124>(k, pk);  // row_ror:4
+    argmax_step_dpp<0x128>(k, pk);  // row_ror:8
+    argmax_step_swap<16>(k, pk);
+    argmax_step_swap<32>(k, pk);
+    pk = __builtin_amdgcn_readfirstlane(pk);
+    id = unpack_id(pk);
+    pos = unpack_pos(pk);
 }
 
 }  // namespace blp

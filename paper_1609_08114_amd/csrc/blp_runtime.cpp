@@ -86,6 +86,36 @@ struct blp_handle_s {
     bool uniform = false;
     bool any_simplex = false, any_box = false;
     int64_t n_box = 0;
+#ifdef BLP_PHASE_TIMERS
+    unsigned long long* timers = nullptr;
+#endif
+    // kernel-variant remap (autotuner); identity by default
+    int remap[kMaxVariants] = {};
+    // captured launch sequence of the last persistent solve
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_sig;
+    DevBuf tune;  // autotuner scratch (sample list + counters)
+    // profiling events: one start/stop pair per kernel class (+1 for binning)
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<char> ev_used;
+    hipError_t ensure_events(int n) {
+        while ((int)ev0.size() < n) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) return e;
+            ev0.push_back(a);
+            ev1.push_back(b);
+        }
+        ev_used.assign(n, 0);
+        return hipSuccess;
+    }
+    hipError_t mark(int cls, bool start, hipStream_t s) {
+        if (!opt.profile) return hipSuccess;
+        if (start) ev_used[cls] = 1;
+        return hipEventRecord(start ? ev0[cls] : ev1[cls], s);
+    }
 };
 
 static blp_error fail(blp_handle h, blp_error code, const char* fmt, ...) {
@@ -159,7 +189,8 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
     }
     h->cu_count = prop.multiProcessorCount;
     h->variants = reg_variants(&h->nreg);
-    if (o.variant >= h->nreg) {
+    for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = v;
+    if (o.variant >= h->nreg || h->nreg > kMaxVariants) {
         delete h;
         return BLP_ERR_ARG;
     }
@@ -172,6 +203,10 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
         if (o.workers_per_cu > 0) occ = std::min(occ, (int)o.workers_per_cu);
         h->reg_workers.push_back(occ * h->cu_count);
     }
+#ifdef BLP_PHASE_TIMERS
+    if (hipMalloc(&h->timers, TM_SLOTS * sizeof(unsigned long long)) == hipSuccess)
+        (void)hipMemset(h->timers, 0, TM_SLOTS * sizeof(unsigned long long));
+#endif
     *out = h;
     return BLP_SUCCESS;
 }
@@ -180,6 +215,22 @@ void blp_destroy(blp_handle h) {
     if (!h) return;
     (void)hipSetDevice(h->opt.device);
     (void)hipDeviceSynchronize();
+#ifdef BLP_PHASE_TIMERS
+    if (h->timers) {
+        unsigned long long t[TM_SLOTS] = {};
+        (void)hipMemcpy(t, h->timers, sizeof t, hipMemcpyDeviceToHost);
+        fprintf(stderr,
+                "[blp timers] LPs %llu pivots %llu | cycles per LP: load %.0f extract %.0f | per pivot: price %.0f "
+                "pubcol %.0f ratio %.0f pivot %.0f\n",
+                t[TM_LPS], t[TM_PIVOTS], t[TM_LPS] ? (double)t[TM_LOAD] / t[TM_LPS] : 0.0,
+                t[TM_LPS] ? (double)t[TM_EXTRACT] / t[TM_LPS] : 0.0,
+                t[TM_PIVOTS] ? (double)t[TM_PRICE] / t[TM_PIVOTS] : 0.0,
+                t[TM_PIVOTS] ? (double)t[TM_PUBCOL] / t[TM_PIVOTS] : 0.0,
+                t[TM_PIVOTS] ? (double)t[TM_RATIO] / t[TM_PIVOTS] : 0.0,
+                t[TM_PIVOTS] ? (double)t[TM_PIVOT] / t[TM_PIVOTS] : 0.0);
+        (void)hipFree(h->timers);
+    }
+#endif
     h->meta.release();
     h->counters.release();
     h->binid.release();
@@ -190,27 +241,29 @@ void blp_destroy(blp_handle h) {
     h->own_obj.release();
     h->own_x.release();
     h->own_y.release();
+    h->tune.release();
+    for (auto e : h->ev0) (void)hipEventDestroy(e);
+    for (auto e : h->ev1) (void)hipEventDestroy(e);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     delete h;
 }
 
 const char* blp_last_error(blp_handle h) { return h ? h->err.c_str() : "null handle"; }
 
-blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* out, void* stream) {
-    if (!h) return BLP_ERR_ARG;
-    h->err.clear();
-    if (!B) return fail(h, BLP_ERR_ARG, "batch is NULL");
-    if (B->count < 0 || B->count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+// Everything one solve needs after validation.
+struct SolvePlan {
+    KParams P{};
+    bool uni = false, any_simplex = false, any_box = false, box_only_uniform = false;
+    int64_t n_box = 0;
+    int gm_ld = 0, gm_cols = 0, gm_workers = 0;
+    size_t gm_lds = 0;
+    std::vector<char> maybe;  // register variants that can receive LPs
+};
+
+// Validation, outputs, metadata upload, workspace sizing.  No kernel launch.
+static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp) {
     const int64_t K = B->count;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(h, hipSetDevice(h->opt.device));
-    h->solved = false;
-    if (K == 0) {
-        h->count = 0;
-        h->solved = true;
-        return BLP_SUCCESS;
-    }
     if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
-    // ---- host-side validation and packed offsets
     const bool uni = B->uniform != 0;
     const int64_t nmeta = uni ? 1 : K;
     h->h_m.assign(B->m, B->m + nmeta);
@@ -263,11 +316,7 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
             ro += h->h_m[k];
             co += h->h_n[k];
         }
-        if (!B->a_off || !B->row_off || !B->col_off) {
-            tot_a = std::max(tot_a, ao);
-            tot_m = std::max(tot_m, ro);
-            tot_n = std::max(tot_n, co);
-        }
+        tot_a = tot_m = tot_n = 0;
         for (int64_t k = 0; k < K; ++k) {
             tot_a = std::max(tot_a, h->h_a_off[k] + (int64_t)h->h_m[k] * h->h_n[k]);
             tot_m = std::max(tot_m, h->h_row_off[k] + h->h_m[k]);
@@ -300,7 +349,8 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
     }
 
     // ---- kernel parameters
-    KParams P{};
+    KParams& P = sp.P;
+    P = KParams{};
     P.count = K;
     P.uniform = uni ? 1 : 0;
     P.um = h->h_m[0];
@@ -341,46 +391,35 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
     P.eps_price = h->opt.eps_price;
     P.eps_piv = h->opt.eps_piv;
     P.eps_feas = h->opt.eps_feas;
-
+#ifdef BLP_PHASE_TIMERS
+    P.timers = h->timers;
+#endif
     const int nreg = h->nreg, nbins = nreg + 2;
-    const int BIN_GM = nreg, BIN_BOX = nreg + 1;
     HIP_TRY(h, h->counters.reserve(sizeof(int32_t) * 4 * nbins));
     int32_t* bin_count = h->counters.as<int32_t>();
-    int32_t* bin_fill = bin_count + nbins;
-    int32_t* bin_head = bin_fill + nbins;
-    int32_t* bin_off = bin_head + nbins;
-    P.bin_off = bin_off;
     P.bin_len = bin_count;
-    P.bin_head = bin_head;
+    P.bin_head = bin_count + 2 * nbins;
+    P.bin_off = bin_count + 3 * nbins;
+    if (h->opt.profile) HIP_TRY(h, h->ensure_events(nbins + 1));
 
-    // ---- binning (not needed for an all-hyperbox uniform batch)
-    const bool box_only_uniform = uni && !any_simplex;
-    if (!box_only_uniform) {
+    sp.uni = uni;
+    sp.any_simplex = any_simplex;
+    sp.any_box = any_box;
+    sp.n_box = n_box;
+    sp.box_only_uniform = uni && !any_simplex;
+    if (!sp.box_only_uniform) {
         HIP_TRY(h, h->binid.reserve(sizeof(int32_t) * K));
         HIP_TRY(h, h->list.reserve(sizeof(int32_t) * K));
-        VariantTable vt{};
-        vt.nreg = nreg;
-        vt.force = h->opt.variant;
-        for (int v = 0; v < nreg && v < kMaxVariants; ++v) {
-            vt.rows[v] = h->variants[v].max_rows;
-            vt.cols[v] = h->variants[v].max_cols;
-        }
-        HIP_TRY(h, launch_reset(bin_count, 3 * nbins, s));
-        HIP_TRY(h, launch_classify(P, vt, h->binid.as<int32_t>(), bin_count, s));
-        HIP_TRY(h, launch_bin_offsets(bin_count, bin_off, nbins, s));
-        HIP_TRY(h, launch_scatter(K, h->binid.as<int32_t>(), bin_off, bin_fill, h->list.as<int32_t>(), s));
         P.list = h->list.as<int32_t>();
-    } else {
-        P.list = nullptr;
     }
 
     // Which register variants can receive an LP?  For a uniform simplex batch
     // only those chosen for some n_art in [0, m]; otherwise all.
-    std::vector<char> maybe(nreg, 0);
+    sp.maybe.assign(nreg, 0);
     if (h->opt.variant >= 0) {
-        maybe[h->opt.variant] = 1;
-    } else if (h->opt.variant == -1) {
-        if (uni && any_simplex) {
+        sp.maybe[h->opt.variant] = 1;
+    } else if (h->opt.variant == -1 && any_simplex) {
+        if (uni) {
             const int m = h->h_m[0], n = h->h_n[0];
             for (int nart = 0; nart <= m; ++nart) {
                 int best = -1;
@@ -393,96 +432,225 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
                             best = v;
                         }
                     }
-                if (best >= 0) maybe[best] = 1;
+                if (best >= 0 && h->remap[best] < nreg) sp.maybe[h->remap[best]] = 1;
             }
-        } else if (any_simplex) {
-            std::fill(maybe.begin(), maybe.end(), 1);
+        } else {
+            std::fill(sp.maybe.begin(), sp.maybe.end(), 1);
         }
     }
     // Streaming-kernel geometry: worst case over the batch's simplex LPs.
-    const int gm_ld = ((max_m + 2 + 63) / 64) * 64;
-    const int gm_cols = max_cols;
-    const size_t gm_lds = any_simplex ? gm_lds_bytes_host(gm_ld, gm_cols) : 0;
-    int gm_workers = 0;
     if (any_simplex) {
+        sp.gm_ld = ((max_m + 2 + 63) / 64) * 64;
+        sp.gm_cols = max_cols;
+        sp.gm_lds = gm_lds_bytes_host(sp.gm_ld, sp.gm_cols);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(), gm_threads(), gm_lds) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(), gm_threads(), sp.gm_lds) !=
+                hipSuccess ||
             occ < 1)
             occ = 1;
         if (h->opt.workers_per_cu > 0) occ = std::min(occ, (int)h->opt.workers_per_cu);
-        gm_workers = occ * h->cu_count;
-        const size_t slot = (size_t)gm_ld * gm_cols;
-        HIP_TRY(h, h->ws.reserve(sizeof(double) * slot * (size_t)gm_workers));
+        sp.gm_workers = occ * h->cu_count;
+        const size_t slot = (size_t)sp.gm_ld * sp.gm_cols;
+        HIP_TRY(h, h->ws.reserve(sizeof(double) * slot * (size_t)sp.gm_workers));
         P.ws = h->ws.as<double>();
         P.ws_slot = (int64_t)slot;
-        P.ws_ld = gm_ld;
-        P.ws_cols = gm_cols;
+        P.ws_ld = sp.gm_ld;
+        P.ws_cols = sp.gm_cols;
     }
+    return BLP_SUCCESS;
+}
 
-    const int mode = h->opt.mode;
-    if (mode == BLP_MODE_PERSISTENT) {
-        P.direct = 0;
-        for (int v = 0; v < nreg; ++v) {
-            if (!maybe[v]) continue;
-            KParams Q = P;
-            Q.bin = v;
-            const int grid = (int)std::min<int64_t>(h->reg_workers[v], K);
-            HIP_TRY(h, h->variants[v].launch(Q, grid, s));
-        }
-        if (any_simplex) {
-            KParams Q = P;
-            Q.bin = BIN_GM;
-            const int grid = (int)std::min<int64_t>(gm_workers, K);
-            HIP_TRY(h, launch_gm(Q, grid, gm_lds, s));
-        }
-    } else {
-        // grid / one-per-launch: read the bins back to size the launches
-        std::vector<int32_t> cnt(nbins, 0);
-        if (!box_only_uniform) {
-            HIP_TRY(h, hipMemcpyAsync(cnt.data(), bin_count, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost, s));
-            HIP_TRY(h, hipStreamSynchronize(s));
-        }
-        P.direct = 1;
-        for (int v = 0; v <= nreg; ++v) {
-            const int64_t nv = cnt[v];
-            if (nv == 0) continue;
-            KParams Q = P;
-            Q.bin = v;
-            const int64_t chunk = v == BIN_GM ? gm_workers : (mode == BLP_MODE_GRID ? nv : 1);
-            for (int64_t first = 0; first < nv; first += chunk) {
-                Q.direct_first = first;
-                const int grid = (int)std::min<int64_t>(chunk, nv - first);
-                if (v == BIN_GM) {
-                    if (mode == BLP_MODE_GRID) {
-                        HIP_TRY(h, launch_gm(Q, grid, gm_lds, s));
-                    } else {
-                        for (int64_t q = first; q < first + grid; ++q) {
-                            Q.direct_first = q;
-                            HIP_TRY(h, launch_gm(Q, 1, gm_lds, s));
-                        }
-                    }
+static VariantTable variant_table(blp_handle h) {
+    VariantTable vt{};
+    vt.nreg = h->nreg;
+    vt.force = h->opt.variant;
+    for (int v = 0; v < h->nreg && v < kMaxVariants; ++v) {
+        vt.rows[v] = h->variants[v].max_rows;
+        vt.cols[v] = h->variants[v].max_cols;
+        vt.remap[v] = h->remap[v];
+    }
+    return vt;
+}
+
+// reset -> classify -> offsets -> scatter
+static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    if (sp.box_only_uniform) return BLP_SUCCESS;
+    const int nbins = h->nreg + 2;
+    int32_t* bin_count = h->counters.as<int32_t>();
+    int32_t* bin_fill = bin_count + nbins;
+    HIP_TRY(h, h->mark(nbins, true, s));
+    HIP_TRY(h, launch_reset(bin_count, 3 * nbins, s));
+    HIP_TRY(h, launch_classify(sp.P, variant_table(h), h->binid.as<int32_t>(), bin_count, s));
+    HIP_TRY(h, launch_bin_offsets(bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
+    HIP_TRY(h, launch_scatter(sp.P.count, nbins, h->binid.as<int32_t>(), sp.P.bin_off, bin_fill,
+                              h->list.as<int32_t>(), s));
+    HIP_TRY(h, h->mark(nbins, false, s));
+    return BLP_SUCCESS;
+}
+
+// One persistent launch per kernel class that can receive LPs.
+static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    const int nreg = h->nreg;
+    const int64_t K = sp.P.count;
+    KParams P = sp.P;
+    P.direct = 0;
+    for (int v = 0; v < nreg; ++v) {
+        if (!sp.maybe[v]) continue;
+        KParams Q = P;
+        Q.bin = v;
+        const int grid = (int)std::min<int64_t>(h->reg_workers[v], K);
+        HIP_TRY(h, h->mark(v, true, s));
+        HIP_TRY(h, h->variants[v].launch(Q, grid, s));
+        HIP_TRY(h, h->mark(v, false, s));
+    }
+    if (sp.any_simplex) {
+        KParams Q = P;
+        Q.bin = nreg;
+        const int grid = (int)std::min<int64_t>(sp.gm_workers, K);
+        HIP_TRY(h, h->mark(nreg, true, s));
+        HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s));
+        HIP_TRY(h, h->mark(nreg, false, s));
+    }
+    return BLP_SUCCESS;
+}
+
+static blp_error enqueue_hyperbox(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    if (!sp.any_box) return BLP_SUCCESS;
+    KParams Q = sp.P;
+    Q.bin = h->nreg + 1;
+    Q.direct = 0;
+    HIP_TRY(h, h->mark(h->nreg + 1, true, s));
+    HIP_TRY(h, launch_hyperbox(Q, sp.box_only_uniform ? sp.P.count : sp.n_box, s));
+    HIP_TRY(h, h->mark(h->nreg + 1, false, s));
+    return BLP_SUCCESS;
+}
+
+// Grid / one-LP-per-launch modes: read the bins back to size the launches.
+static blp_error enqueue_baseline(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    const int nreg = h->nreg, nbins = nreg + 2, mode = h->opt.mode;
+    std::vector<int32_t> cnt(nbins, 0);
+    if (!sp.box_only_uniform) {
+        HIP_TRY(h, hipMemcpyAsync(cnt.data(), sp.P.bin_len, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+    }
+    KParams P = sp.P;
+    P.direct = 1;
+    for (int v = 0; v <= nreg; ++v) {
+        const int64_t nv = cnt[v];
+        if (nv == 0) continue;
+        KParams Q = P;
+        Q.bin = v;
+        const int64_t chunk = v == nreg ? sp.gm_workers : (mode == BLP_MODE_GRID ? nv : 1);
+        HIP_TRY(h, h->mark(v, true, s));
+        for (int64_t first = 0; first < nv; first += chunk) {
+            Q.direct_first = first;
+            const int grid = (int)std::min<int64_t>(chunk, nv - first);
+            if (v == nreg) {
+                if (mode == BLP_MODE_GRID) {
+                    HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s));
                 } else {
-                    HIP_TRY(h, h->variants[v].launch(Q, grid, s));
+                    for (int64_t q = first; q < first + grid; ++q) {
+                        Q.direct_first = q;
+                        HIP_TRY(h, launch_gm(Q, 1, sp.gm_lds, s));
+                    }
                 }
+            } else {
+                HIP_TRY(h, h->variants[v].launch(Q, grid, s));
             }
         }
-        P.direct = 0;
+        HIP_TRY(h, h->mark(v, false, s));
     }
-    if (any_box) {
-        KParams Q = P;
-        Q.bin = BIN_BOX;
-        Q.direct = 0;
-        HIP_TRY(h, launch_hyperbox(Q, box_only_uniform ? K : n_box, s));
+    return BLP_SUCCESS;
+}
+
+// Signature of everything a captured launch sequence depends on.
+static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, hipStream_t s) {
+    const KParams& P = sp.P;
+    std::vector<uint64_t> g = {(uint64_t)(uintptr_t)s, (uint64_t)P.count, (uint64_t)P.uniform, (uint64_t)P.um,
+                               (uint64_t)P.un, (uint64_t)P.ukind, (uint64_t)(uintptr_t)P.A, (uint64_t)(uintptr_t)P.b,
+                               (uint64_t)(uintptr_t)P.sense, (uint64_t)(uintptr_t)P.c, (uint64_t)(uintptr_t)P.l,
+                               (uint64_t)(uintptr_t)P.u, (uint64_t)(uintptr_t)P.status,
+                               (uint64_t)(uintptr_t)P.iters, (uint64_t)(uintptr_t)P.obj, (uint64_t)(uintptr_t)P.x,
+                               (uint64_t)(uintptr_t)P.y, (uint64_t)(uintptr_t)P.list, (uint64_t)(uintptr_t)P.bin_len,
+                               (uint64_t)(uintptr_t)P.ws, (uint64_t)P.ws_slot, (uint64_t)P.ws_ld,
+                               (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)h->binid.p,
+                               (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers};
+    for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
+    if (!sp.uni) {
+        // metadata content (the device copy is refreshed on every call, but
+        // the launch shapes depend only on what is compared here)
+        uint64_t f = 1469598103934665603ull;
+        auto mix = [&](const void* p, size_t n) {
+            const unsigned char* c = static_cast<const unsigned char*>(p);
+            for (size_t i = 0; i < n; ++i) f = (f ^ c[i]) * 1099511628211ull;
+        };
+        mix(h->h_kind.data(), h->h_kind.size() * sizeof(int32_t));
+        g.push_back(f);
+    }
+    return g;
+}
+
+blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* out, void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (!B) return fail(h, BLP_ERR_ARG, "batch is NULL");
+    if (B->count < 0 || B->count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    const int64_t K = B->count;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    h->solved = false;
+    if (K == 0) {
+        h->count = 0;
+        h->solved = true;
+        return BLP_SUCCESS;
+    }
+    SolvePlan sp;
+    blp_error e = prepare(h, B, out, s, sp);
+    if (e != BLP_SUCCESS) return e;
+
+    const bool use_graph = h->opt.graph && !h->opt.profile && h->opt.mode == BLP_MODE_PERSISTENT;
+    if (use_graph) {
+        std::vector<uint64_t> sig = graph_signature(h, sp, s);
+        if (!h->graph_exec || sig != h->graph_sig) {
+            if (h->graph_exec) {
+                (void)hipGraphExecDestroy(h->graph_exec);
+                h->graph_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            blp_error ce = enqueue_binning(h, sp, s);
+            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, s);
+            if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, s);
+            hipError_t he = hipStreamEndCapture(s, &g);
+            if (ce != BLP_SUCCESS) {
+                if (g) (void)hipGraphDestroy(g);
+                return ce;
+            }
+            HIP_TRY(h, he);
+            hipError_t ie = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(h, ie);
+            h->graph_sig = sig;
+        }
+        HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
+    } else {
+        e = enqueue_binning(h, sp, s);
+        if (e != BLP_SUCCESS) return e;
+        e = h->opt.mode == BLP_MODE_PERSISTENT ? enqueue_persistent(h, sp, s) : enqueue_baseline(h, sp, s);
+        if (e != BLP_SUCCESS) return e;
+        e = enqueue_hyperbox(h, sp, s);
+        if (e != BLP_SUCCESS) return e;
     }
     HIP_TRY(h, hipGetLastError());
 
-    h->last = P;
+    h->last = sp.P;
+    h->last.direct = 0;
     h->last_stream = s;
     h->count = K;
-    h->uniform = uni;
-    h->any_simplex = any_simplex;
-    h->any_box = any_box;
-    h->n_box = n_box;
+    h->uniform = sp.uni;
+    h->any_simplex = sp.any_simplex;
+    h->any_box = sp.any_box;
+    h->n_box = sp.n_box;
     h->solved = true;
     return BLP_SUCCESS;
 }
@@ -564,6 +732,180 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
         KParams Q = P;
         Q.bin = h->nreg + 1;
         HIP_TRY(h, launch_backward_hyperbox(Q, P.list ? h->n_box : h->count, g, dc, dl, du, s));
+    }
+    return BLP_SUCCESS;
+}
+
+// ---------------------------------------------------------------- autotuner
+static blp_error write_tuning(blp_handle h, const char* path) {
+    hipDeviceProp_t prop;
+    HIP_TRY(h, hipGetDeviceProperties(&prop, h->opt.device));
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(h, BLP_ERR_ARG, "cannot write %s", path);
+    std::fprintf(f, "{\n  \"arch\": \"%s\",\n  \"cus\": %d,\n  \"remap\": {", prop.gcnArchName, h->cu_count);
+    for (int v = 0; v < h->nreg; ++v)
+        std::fprintf(f, "%s\n    \"%s\": \"%s\"", v ? "," : "", h->variants[v].name,
+                     h->remap[v] < h->nreg ? h->variants[h->remap[v]].name : "streaming");
+    std::fprintf(f, "\n  }\n}\n");
+    std::fclose(f);
+    return BLP_SUCCESS;
+}
+
+blp_error blp_load_tuning(blp_handle h, const char* path) {
+    if (!h || !path) return BLP_ERR_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(h, BLP_ERR_ARG, "cannot read %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t nr;
+    while ((nr = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, nr);
+    std::fclose(f);
+    hipDeviceProp_t prop;
+    HIP_TRY(h, hipGetDeviceProperties(&prop, h->opt.device));
+    char want[256];
+    std::snprintf(want, sizeof want, "\"arch\": \"%s\"", prop.gcnArchName);
+    char cus[64];
+    std::snprintf(cus, sizeof cus, "\"cus\": %d", h->cu_count);
+    if (txt.find(want) == std::string::npos || txt.find(cus) == std::string::npos)
+        return fail(h, BLP_ERR_ARG, "%s was tuned for another device", path);
+    auto index_of = [&](const std::string& name) {
+        if (name == "streaming") return h->nreg;
+        for (int v = 0; v < h->nreg; ++v)
+            if (name == h->variants[v].name) return v;
+        return -1;
+    };
+    int remap[kMaxVariants];
+    for (int v = 0; v < kMaxVariants; ++v) remap[v] = v;
+    for (int v = 0; v < h->nreg; ++v) {
+        const std::string key = std::string("\"") + h->variants[v].name + "\": \"";
+        const size_t p = txt.find(key);
+        if (p == std::string::npos) continue;
+        const size_t q = txt.find('"', p + key.size());
+        if (q == std::string::npos) return fail(h, BLP_ERR_ARG, "malformed %s", path);
+        const int w = index_of(txt.substr(p + key.size(), q - p - key.size()));
+        if (w < 0) return fail(h, BLP_ERR_ARG, "unknown variant in %s", path);
+        // a replacement must hold every LP of the original bin
+        if (w < h->nreg && (h->variants[w].max_rows < h->variants[v].max_rows ||
+                            h->variants[w].max_cols < h->variants[v].max_cols))
+            return fail(h, BLP_ERR_ARG, "%s maps %s to a smaller variant", path, h->variants[v].name);
+        remap[v] = w;
+    }
+    for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = remap[v];
+    if (h->graph_exec) {
+        (void)hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+    return BLP_SUCCESS;
+}
+
+blp_error blp_tuning(blp_handle h, int32_t* remap, int32_t* n_reg) {
+    if (!h) return BLP_ERR_ARG;
+    if (n_reg) *n_reg = h->nreg;
+    if (remap)
+        for (int v = 0; v < h->nreg; ++v) remap[v] = h->remap[v];
+    return BLP_SUCCESS;
+}
+
+blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const char* cache_path, void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (!B || B->count <= 0 || sample <= 0) return fail(h, BLP_ERR_ARG, "autotune needs a non-empty batch and sample > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    const int nreg = h->nreg, nbins = nreg + 2;
+    // classify with the untuned table
+    int saved[kMaxVariants];
+    for (int v = 0; v < kMaxVariants; ++v) {
+        saved[v] = h->remap[v];
+        h->remap[v] = v;
+    }
+    const int saved_force = h->opt.variant;
+    h->opt.variant = -1;
+    SolvePlan sp;
+    blp_error e = prepare(h, B, nullptr, s, sp);
+    if (e == BLP_SUCCESS) e = enqueue_binning(h, sp, s);
+    h->opt.variant = saved_force;
+    if (e != BLP_SUCCESS || sp.box_only_uniform) {
+        for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = saved[v];
+        return e;
+    }
+    std::vector<int32_t> cnt(nbins), off(nbins);
+    HIP_TRY(h, hipMemcpyAsync(cnt.data(), sp.P.bin_len, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(off.data(), sp.P.bin_off, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    for (int v = 0; v < nreg; ++v) {
+        if (cnt[v] == 0) continue;
+        const int S = std::min<int>(sample, cnt[v]);
+        // scratch: [bin_off = 0, bin_len = S, bin_head] + S list entries
+        HIP_TRY(h, h->tune.reserve(sizeof(int32_t) * (4 + (size_t)S)));
+        int32_t* tb = h->tune.as<int32_t>();
+        int32_t hdr[3] = {0, S, 0};
+        HIP_TRY(h, hipMemcpyAsync(tb, hdr, sizeof hdr, hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(tb + 4, h->list.as<int32_t>() + off[v], sizeof(int32_t) * S,
+                                  hipMemcpyDeviceToDevice, s));
+        KParams Q = sp.P;
+        Q.list = tb + 4;
+        Q.bin_off = tb;
+        Q.bin_len = tb + 1;
+        Q.bin_head = tb + 2;
+        Q.bin = 0;
+        Q.direct = 0;
+        float best_ms = -1.f;
+        int best = v;
+        for (int w = 0; w <= nreg; ++w) {
+            if (w < nreg && (h->variants[w].max_rows < h->variants[v].max_rows ||
+                             h->variants[w].max_cols < h->variants[v].max_cols))
+                continue;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+                HIP_TRY(h, launch_reset(tb + 2, 1, s));
+                HIP_TRY(h, hipEventRecord(e0, s));
+                if (w < nreg) {
+                    HIP_TRY(h, h->variants[w].launch(Q, (int)std::min<int64_t>(h->reg_workers[w], S), s));
+                } else {
+                    HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, S), sp.gm_lds, s));
+                }
+                HIP_TRY(h, hipEventRecord(e1, s));
+                HIP_TRY(h, hipEventSynchronize(e1));
+                HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+            }
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best = w;
+            }
+        }
+        saved[v] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = saved[v];
+    if (h->graph_exec) {
+        (void)hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+    h->solved = false;  // the handle's outputs hold tuning runs, not a solve
+    if (cache_path) return write_tuning(h, cache_path);
+    return BLP_SUCCESS;
+}
+
+blp_error blp_last_kernel_ms(blp_handle h, double* ms, int32_t* n_entries) {
+    if (!h) return BLP_ERR_ARG;
+    const int n = h->nreg + 3;
+    if (n_entries) *n_entries = n;
+    if (!ms) return BLP_SUCCESS;
+    for (int i = 0; i < n; ++i) ms[i] = 0.0;
+    if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
+    if (!h->opt.profile || h->count == 0) return BLP_SUCCESS;
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    for (int i = 0; i < n && i < (int)h->ev_used.size(); ++i) {
+        if (!h->ev_used[i]) continue;
+        float t = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&t, h->ev0[i], h->ev1[i]));
+        ms[i] = t;
     }
     return BLP_SUCCESS;
 }

@@ -54,6 +54,10 @@ simplex_reg_kernel(KParams P) {
     __shared__ int s_colvar[CP], s_basis[RP], s_artrow[RP], s_rank[RP];
     __shared__ unsigned char s_flag[RP];
     __shared__ int s_k, s_nart, s_bad;
+    // Staging area for building the initial tableau, SR rows at a time
+    // (row-major, CP columns), filled with coalesced loads.
+    constexpr int SR = RP < 32 ? RP : 32;
+    __shared__ double s_T[SR * CP];
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -63,6 +67,7 @@ simplex_reg_kernel(KParams P) {
     chunk T[NCH];
 #define TV(c) T[(c) / CK][(c) % CK]
 
+    BLP_TDECL;
     const int64_t len = work_len(P);
     bool first = true;
     for (;;) {
@@ -79,6 +84,7 @@ simplex_reg_kernel(KParams P) {
         __syncthreads();
         const int k = s_k;
         if (k < 0) break;
+        BLP_T(t_load0);
 
         // ------------------------------------------------------------ load
         const LpRef L = lp_ref(P, k);
@@ -98,7 +104,7 @@ simplex_reg_kernel(KParams P) {
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
         __syncthreads();
         const int nart = s_nart;
-        if (m > RP - 2 || n + nart + 1 > CP) {
+        if (n + nart + 1 > CP) {
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
             __syncthreads();
             continue;
@@ -121,34 +127,38 @@ simplex_reg_kernel(KParams P) {
                 s_p[j] = acc;
             }
         }
-        __syncthreads();
-        {
-            // Branch-free fill (every load address is valid; selects pick the
-            // value), so the register tile is never merged across branches.
-            const int i = tr;
-            const bool rowok = i < m;
-            const double sg = rowok ? s_sig[i] : 0.0;
-            const double rhs = rowok ? s_b[i] : 0.0;
-            const int sur = rowok && (s_flag[i] & RF_ART) ? n + s_rank[i] : -1;
-            const double* arow = P.A + L.a_off + (int64_t)(rowok ? i : 0) * n;
-            const double* crow = P.c + L.col_off;
-            const bool objrow = i == ROW_OBJ, wrow = i == ROW_W && nart > 0;
+        // Initial tableau, SR rows at a time: built element-wise in LDS with
+        // coalesced loads, then each thread whose row is in the chunk copies
+        // its column block (a select keeps the tile out of divergent branches).
+        for (int r0 = 0; r0 < RP; r0 += SR) {
+            __syncthreads();
+            for (int e = t; e < SR * CP; e += NT) {
+                const int i = r0 + e / CP, j = e - (e / CP) * CP;
+                double v = 0.0;
+                if (i < m) {
+                    if (j < n) {
+                        const double a = P.A[L.a_off + (int64_t)i * n + j];
+                        bad |= !isfinite(a);
+                        v = s_sig[i] * a;
+                    } else if (j < n + nart) {
+                        v = s_artrow[j - n] == i ? -1.0 : 0.0;
+                    } else if (j == COL_RHS) {
+                        v = s_b[i];
+                    }
+                } else if (i == ROW_OBJ) {
+                    v = j < n ? P.c[L.col_off + j] : 0.0;
+                } else if (i == ROW_W && nart > 0) {
+                    v = s_p[j];
+                }
+                s_T[e] = v;
+            }
+            __syncthreads();
+            const bool mine = tr >= r0 && tr < r0 + SR;
+            const double* src = s_T + (mine ? tr - r0 : 0) * CP + j0;
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
-                const int j = j0 + c;
-                const int jj = j < n ? j : n - 1;
-                const double a = arow[jj];
-                const double cj = crow[jj];
-                const double w = s_p[j];
-                double v = 0.0;
-                v = rowok && j < n ? sg * a : v;
-                v = j == sur ? -1.0 : v;
-                v = rowok && j == COL_RHS ? rhs : v;
-                v = objrow && j < n ? cj : v;
-                v = wrow ? w : v;
-                bad |= rowok && j < n && !isfinite(a);
-                TV(c) = v;
-                if (c % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight
+                const double v = src[c];
+                TV(c) = mine ? v : TV(c);
             }
         }
         if (bad) atomicOr(&s_bad, 1);
@@ -241,9 +251,12 @@ simplex_reg_kernel(KParams P) {
         // One loop, one pivot site: mode 1 = phase 1, 2 = phase 2, 3 = driving
         // the remaining basic artificials out after a feasible phase 1.
         int mode = phase, drive_r = 0;
+        BLP_T(t_load1);
+        BLP_TACC(TM_LOAD, t_load0, t_load1);
         for (;;) {
             int e_id, e, l = -1;
             double rmin = 1.0;
+            BLP_T(t_p0);
             if (mode == 3) {
                 int r0 = -1;
                 for (; drive_r < m; ++drive_r)
@@ -308,7 +321,9 @@ simplex_reg_kernel(KParams P) {
                     break;
                 }
             }
+            BLP_T(t_p1);
             publish_col(e);
+            BLP_T(t_p2);
             if (mode != 3) {
                 l = ratio_test(m, lane, P.eps_piv, s_f, s_b, s_basis, s_flag, rmin);
                 if (l < 0) {
@@ -316,12 +331,19 @@ simplex_reg_kernel(KParams P) {
                     break;
                 }
             }
+            BLP_T(t_p3);
             pivot(l, e, e_id, s_f[l]);
+            BLP_T(t_p4);
+            BLP_TACC(TM_PRICE, t_p0, t_p1);
+            BLP_TACC(TM_PUBCOL, t_p1, t_p2);
+            BLP_TACC(TM_RATIO, t_p2, t_p3);
+            BLP_TACC(TM_PIVOT, t_p3, t_p4);
             ++iters;
             if (mode != 3) degen = rmin == 0.0 ? degen + 1 : 0;
         }
 
         // ------------------------------------------------------ extraction
+        BLP_T(t_x0);
         if (tr == ROW_OBJ) {
 #pragma unroll
             for (int c = 0; c < CT; ++c) s_d[j0 + c] = TV(c);
@@ -329,7 +351,12 @@ simplex_reg_kernel(KParams P) {
         __syncthreads();
         write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, COL_RHS, s_d, s_b, s_colvar, s_basis, s_flag, s_p, s_f);
         __syncthreads();
+        BLP_T(t_x1);
+        BLP_TACC(TM_EXTRACT, t_x0, t_x1);
+        BLP_TCOUNT(TM_PIVOTS, (unsigned long long)iters);
+        BLP_TCOUNT(TM_LPS, 1ull);
     }
+    BLP_TFLUSH();
 #undef TV
 }
 

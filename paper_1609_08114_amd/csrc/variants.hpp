@@ -25,7 +25,7 @@ const RegVariant* reg_variants(int* count);
 
 // clang-format off
 #define BLP_REG_VARIANT_LIST                                  \
-    BLP_REG_VARIANT("w1_r8_c8",      1, 8,   1, 8)           \
+    BLP_REG_VARIANT("w1_r8_c8",      1, 8,   1, 4)           \
     BLP_REG_VARIANT("w1_r16_c16",    1, 4,   4, 4)           \
     BLP_REG_VARIANT("w1_r32_c32",    1, 2,  16, 2)           \
     BLP_REG_VARIANT("w2_r64_c64",    2, 2,  32, 1)           \

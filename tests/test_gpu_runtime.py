@@ -1,0 +1,129 @@
+"""Runtime features on the GPU: hipGraph replay, autotuner, profiling hooks,
+error paths that reach the device."""
+import json
+
+import numpy as np
+import pytest
+
+import lpgen
+from solve_util import gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(a):
+    return np.asarray(a).view(np.int64)
+
+
+def test_graph_replay_matches_eager():
+    import torch
+
+    import paper_1609_08114_amd as blp
+    hb = lpgen.config(4, range(500, 620))
+    ref = gpu_solve(hb)
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver(graph=True)
+    outs = []
+    for rep in range(4):
+        out = s.solve(db)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1000, device="cuda").sum().item()
+        outs.append({k: v.cpu().numpy().copy() for k, v in out.items()})
+    # a different batch forces a new capture, then the first one again
+    hb2 = lpgen.config(1, range(100))
+    out2 = s.solve(blp.DeviceBatch.from_host(hb2))
+    torch.cuda.synchronize()
+    ref2 = gpu_solve(hb2)
+    assert np.array_equal(_bits(out2["obj"][:100].cpu().numpy()), _bits(ref2["obj"]))
+    out3 = s.solve(db)
+    torch.cuda.synchronize()
+    outs.append({k: v.cpu().numpy().copy() for k, v in out3.items()})
+    s.close()
+    K = hb.count
+    for o in outs:
+        assert np.array_equal(o["status"][:K], ref["status"])
+        assert np.array_equal(_bits(o["obj"][:K]), _bits(ref["obj"]))
+        assert np.array_equal(_bits(o["x"][:hb.c.size]), _bits(ref["x"][:hb.c.size]))
+
+
+def test_autotune_remap_and_cache(tmp_path):
+    import torch
+
+    import paper_1609_08114_amd as blp
+    hb = lpgen.config(4, range(700, 900))
+    db = blp.DeviceBatch.from_host(hb)
+    ref = gpu_solve(hb)
+    s = blp.Solver()
+    path = str(tmp_path / "tune.json")
+    s.autotune(db, sample=32, cache_path=path)
+    remap = blp.blp_tuning(s.h)
+    vs = blp.variants()
+    for v, w in enumerate(remap):
+        if w < len(vs):
+            assert vs[w][1] >= vs[v][1] and vs[w][2] >= vs[v][2]
+    tab = json.load(open(path))
+    assert tab["cus"] > 0 and set(tab["remap"]) == {v[0] for v in vs}
+    out = s.solve(db)
+    torch.cuda.synchronize()
+    K = hb.count
+    assert np.array_equal(out["status"][:K].cpu().numpy(), ref["status"])
+    assert np.array_equal(_bits(out["obj"][:K].cpu().numpy()), _bits(ref["obj"]))
+    s.close()
+    s2 = blp.Solver()
+    blp.blp_load_tuning(s2.h, path)
+    assert np.array_equal(blp.blp_tuning(s2.h), remap)
+    s2.close()
+
+
+def test_profile_and_bins():
+    import torch
+
+    import paper_1609_08114_amd as blp
+    hb = lpgen.config(4, range(0, 300))
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver(profile=True)
+    s.solve(db)
+    ms = blp.blp_last_kernel_ms(s.h)
+    bins = blp.blp_last_bins(s.h)
+    s.close()
+    assert bins.sum() == 300
+    assert (ms >= 0).all() and ms.sum() > 0
+    assert len(ms) == len(bins) + 1
+
+
+def test_errors_from_the_device_side():
+    import torch
+
+    import paper_1609_08114_amd as blp
+    s = blp.Solver()
+    hb = lpgen.config(1, range(4))
+    db = blp.DeviceBatch.from_host(hb)
+    bad = db.c_struct()
+    bad.A = None
+    with pytest.raises(blp.BlpError) as ei:
+        blp.blp_solve_batch(s.h, bad)
+    assert ei.value.code == blp.BLP_ERR_ARG
+    # backward before any solve
+    s2 = blp.Solver()
+    g = torch.ones(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(blp.BlpError) as ei:
+        blp.blp_backward(s2.h, blp._ptr(g))
+    assert ei.value.code == blp.BLP_ERR_STATE
+    # too large
+    hb_big = lpgen.make_batch(1, [0], [1], [2047], [3])
+    dbb = blp.DeviceBatch.from_host(hb_big)
+    with pytest.raises(blp.BlpError) as ei:
+        s.solve(dbb)
+    assert ei.value.code == blp.BLP_ERR_TOO_LARGE
+    # get_solution copies one LP to the host
+    s.solve(db)
+    st = np.zeros(1, np.int32)
+    ob = np.zeros(1)
+    x = np.zeros(5)
+    blp.blp_get_solution(s.h, 2, st.ctypes.data_as(blp.ctypes.c_void_p), ob.ctypes.data_as(blp.ctypes.c_void_p),
+                         x.ctypes.data_as(blp.ctypes.c_void_p), None, None)
+    ref = gpu_solve(hb)
+    assert st[0] == 0 and ob[0] == ref["obj"][2]
+    s.close()
+    s2.close()
