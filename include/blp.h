@@ -92,7 +92,17 @@ typedef struct {
     int32_t profile;       /* nonzero: record HIP events around each kernel class (blp_last_kernel_ms) */
     int32_t graph;         /* nonzero (persistent mode): capture the launch sequence into a hipGraph
                               per batch signature and replay it when the same batch recurs */
+    int32_t pivot_rule;    /* BLP_RULE_LPC (default) or BLP_RULE_RPC */
+    int32_t reserved_;
+    uint64_t seed;         /* RPC only: Philox4x32-10 key; draw = (seed, LP index, pivot count) */
 } blp_options;
+
+/* Entering rules (Sec. 4.2).  LPC: largest positive reduced cost (Dantzig),
+ * lowest variable index on ties.  RPC: a uniformly random column among those
+ * with a positive reduced cost, drawn deterministically from Philox4x32-10
+ * keyed by the seed and addressed by (LP index, pivot count); the optimum is
+ * the same, the pivot path and count differ. */
+enum { BLP_RULE_LPC = 0, BLP_RULE_RPC = 1 };
 
 /* A batch.  LP k has m[k] rows and n[k] columns (hyperbox: m[k] = 0).
  * Metadata arrays are HOST memory; data arrays are DEVICE memory.
@@ -154,6 +164,17 @@ blp_error blp_create(blp_handle* out, const blp_options* opt);
  * The handle remembers the batch and output pointers for blp_backward and
  * blp_get_solution*, until the next solve. */
 blp_error blp_solve_batch(blp_handle h, const blp_batch* batch, const blp_outputs* out, void* hip_stream);
+
+/* Host-resident batch with copy/compute overlap (the stream scheme of
+ * Sec. 4.4).  Same batch description as blp_solve_batch except that the
+ * data arrays (A, b, sense, c, l, u) are HOST memory (page-locked memory
+ * gives asynchronous copies) and `out` points to HOST buffers (all five
+ * required).  The batch is cut into `chunks` pieces (<= 0: automatic); each
+ * piece's upload, solve and download are issued on one of two streams in
+ * turn, so transfers of one piece overlap the kernels of the other.
+ * Synchronous: returns when every result is in host memory.  Afterwards
+ * blp_get_solution* and blp_backward refer to the last piece only. */
+blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_outputs* out, int32_t chunks);
 
 /* Copy LP k's results of the last solve to HOST memory (synchronises the
  * solve's stream).  x (length n) and y (length m) may be NULL. */

@@ -22,19 +22,22 @@ BLP_KIND_SIMPLEX, BLP_KIND_HYPERBOX = 0, 1
 BLP_OPTIMAL, BLP_INFEASIBLE, BLP_UNBOUNDED, BLP_ITER_LIMIT, BLP_NUMERICAL = range(5)
 BLP_SUCCESS, BLP_ERR_ARG, BLP_ERR_NOMEM, BLP_ERR_HIP, BLP_ERR_STATE, BLP_ERR_TOO_LARGE = range(6)
 BLP_MODE_PERSISTENT, BLP_MODE_GRID, BLP_MODE_ONE_PER_LAUNCH = range(3)
+BLP_RULE_LPC, BLP_RULE_RPC = range(2)
 ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_STATE", 5: "ERR_TOO_LARGE"}
 
 # Every entry point that include/blp.h declares.
 EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
-           "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning"]
+           "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning",
+           "blp_solve_batch_host"]
 
 
 class blp_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("bland_after", ctypes.c_int32), ("eps_price", ctypes.c_double), ("eps_piv", ctypes.c_double),
                 ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("graph", ctypes.c_int32), ("pivot_rule", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class blp_batch(ctypes.Structure):
@@ -86,6 +89,7 @@ def lib() -> ctypes.CDLL:
         L.blp_autotune.argtypes = [vp, P(blp_batch), i32, ctypes.c_char_p, vp]
         L.blp_load_tuning.argtypes = [vp, ctypes.c_char_p]
         L.blp_tuning.argtypes = [vp, vp, P(i32)]
+        L.blp_solve_batch_host.argtypes = [vp, P(blp_batch), P(blp_outputs), i32]
         for f in EXPORTS:
             if f not in ("blp_abi_version", "blp_destroy", "blp_last_error"):
                 getattr(L, f).restype = ctypes.c_int
@@ -123,6 +127,10 @@ def blp_last_error(h) -> str:
 def blp_solve_batch(h, batch: blp_batch, out: blp_outputs | None = None, stream: int | None = None) -> None:
     _check(h, lib().blp_solve_batch(h, ctypes.byref(batch), ctypes.byref(out) if out is not None else None,
                                     stream))
+
+
+def blp_solve_batch_host(h, batch: blp_batch, out: blp_outputs, chunks: int = 0) -> None:
+    _check(h, lib().blp_solve_batch_host(h, ctypes.byref(batch), ctypes.byref(out), chunks))
 
 
 def blp_get_solution(h, k: int, status=None, obj=None, x=None, y=None, iters=None) -> None:
@@ -257,11 +265,13 @@ class Solver:
     """A handle plus device result tensors.  One per host thread."""
 
     def __init__(self, device: int = 0, mode: int = BLP_MODE_PERSISTENT, variant: int = -1, max_iter: int = 0,
-                 workers_per_cu: int = 0, bland_after: int = 0, profile: bool = False, graph: bool = False):
+                 workers_per_cu: int = 0, bland_after: int = 0, profile: bool = False, graph: bool = False,
+                 pivot_rule: int = BLP_RULE_LPC, seed: int = 0):
         o = blp_options_default()
         o.device, o.mode, o.variant, o.max_iter = device, mode, variant, max_iter
         o.workers_per_cu, o.bland_after, o.profile = workers_per_cu, bland_after, 1 if profile else 0
         o.graph = 1 if graph else 0
+        o.pivot_rule, o.seed = pivot_rule, seed
         self.device = device
         self.h = blp_create(o)
 

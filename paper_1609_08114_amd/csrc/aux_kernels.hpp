@@ -33,7 +33,7 @@ hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const d
 
 // Streaming kernel (simplex_gm.hip).
 hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s);
-const void* gm_kernel_ptr();
+const void* gm_kernel_ptr(int ld);
 int gm_threads();
 size_t gm_lds_bytes_host(int ld, int cols);
 

@@ -54,10 +54,13 @@ struct KParams {
     // streaming kernel workspace: one slot of ws_slot doubles per workgroup
     double* ws;
     int64_t ws_slot;
-    int32_t ws_ld;   // leading dimension (rows, multiple of 64)
+    int32_t ws_ld;   // leading dimension (rows, multiple of 16)
     int32_t ws_cols; // columns available per slot
     // phase cycle counters (only with -DBLP_PHASE_TIMERS; NULL otherwise)
     unsigned long long* timers;
+    // entering rule: 0 largest coefficient, 1 random positive coefficient
+    int32_t pivot_rule;
+    uint64_t seed;
 };
 
 // Optional in-kernel phase timers (s_memtime cycles of wave 0, summed over

@@ -94,7 +94,13 @@ struct blp_handle_s {
     // captured launch sequence of the last persistent solve
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_sig;
+    hipStream_t cap_stream = nullptr;
     DevBuf tune;  // autotuner scratch (sample list + counters)
+    // host-resident pipeline: two child handles (own buffers), two streams,
+    // two device input/output sets
+    blp_handle_s* child[2] = {nullptr, nullptr};
+    hipStream_t pipe[2] = {nullptr, nullptr};
+    DevBuf pin_in[2], pin_out[2];
     // profiling events: one start/stop pair per kernel class (+1 for binning)
     std::vector<hipEvent_t> ev0, ev1;
     std::vector<char> ev_used;
@@ -171,6 +177,7 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
     blp_options_default(&o);
     if (opt) o = *opt;
     if (o.mode < 0 || o.mode > 2 || o.variant < -2 || o.workers_per_cu < 0) return BLP_ERR_ARG;
+    if (o.pivot_rule != BLP_RULE_LPC && o.pivot_rule != BLP_RULE_RPC) return BLP_ERR_ARG;
     if (!(o.eps_price >= 0) || !(o.eps_piv >= 0) || !(o.eps_feas >= 0)) return BLP_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return BLP_ERR_HIP;
@@ -242,9 +249,16 @@ void blp_destroy(blp_handle h) {
     h->own_x.release();
     h->own_y.release();
     h->tune.release();
+    for (int i = 0; i < 2; ++i) {
+        if (h->child[i]) blp_destroy(h->child[i]);
+        if (h->pipe[i]) (void)hipStreamDestroy(h->pipe[i]);
+        h->pin_in[i].release();
+        h->pin_out[i].release();
+    }
     for (auto e : h->ev0) (void)hipEventDestroy(e);
     for (auto e : h->ev1) (void)hipEventDestroy(e);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
 
@@ -391,6 +405,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.eps_price = h->opt.eps_price;
     P.eps_piv = h->opt.eps_piv;
     P.eps_feas = h->opt.eps_feas;
+    P.pivot_rule = h->opt.pivot_rule;
+    P.seed = h->opt.seed;
 #ifdef BLP_PHASE_TIMERS
     P.timers = h->timers;
 #endif
@@ -440,11 +456,11 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     }
     // Streaming-kernel geometry: worst case over the batch's simplex LPs.
     if (any_simplex) {
-        sp.gm_ld = ((max_m + 2 + 63) / 64) * 64;
+        sp.gm_ld = ((max_m + 2 + 15) / 16) * 16;  // 128-byte aligned columns
         sp.gm_cols = max_cols;
         sp.gm_lds = gm_lds_bytes_host(sp.gm_ld, sp.gm_cols);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(), gm_threads(), sp.gm_lds) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld), gm_threads(), sp.gm_lds) !=
                 hipSuccess ||
             occ < 1)
             occ = 1;
@@ -566,7 +582,8 @@ static blp_error enqueue_baseline(blp_handle h, SolvePlan& sp, hipStream_t s) {
 // Signature of everything a captured launch sequence depends on.
 static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, hipStream_t s) {
     const KParams& P = sp.P;
-    std::vector<uint64_t> g = {(uint64_t)(uintptr_t)s, (uint64_t)P.count, (uint64_t)P.uniform, (uint64_t)P.um,
+    (void)s;
+    std::vector<uint64_t> g = {(uint64_t)P.count, (uint64_t)P.uniform, (uint64_t)P.um,
                                (uint64_t)P.un, (uint64_t)P.ukind, (uint64_t)(uintptr_t)P.A, (uint64_t)(uintptr_t)P.b,
                                (uint64_t)(uintptr_t)P.sense, (uint64_t)(uintptr_t)P.c, (uint64_t)(uintptr_t)P.l,
                                (uint64_t)(uintptr_t)P.u, (uint64_t)(uintptr_t)P.status,
@@ -576,6 +593,8 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
                                (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)h->binid.p,
                                (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers};
     for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
+    g.push_back((uint64_t)P.pivot_rule);
+    g.push_back(P.seed);
     if (!sp.uni) {
         // metadata content (the device copy is refreshed on every call, but
         // the launch shapes depend only on what is compared here)
@@ -616,12 +635,17 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
                 (void)hipGraphExecDestroy(h->graph_exec);
                 h->graph_exec = nullptr;
             }
+            // Capture on an internal stream (the caller's may be the legacy
+            // default stream, which cannot capture); the graph is then
+            // launched on the caller's stream.
+            if (!h->cap_stream) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            hipStream_t cs = h->cap_stream;
             hipGraph_t g = nullptr;
-            HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            blp_error ce = enqueue_binning(h, sp, s);
-            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, s);
-            if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, s);
-            hipError_t he = hipStreamEndCapture(s, &g);
+            HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            blp_error ce = enqueue_binning(h, sp, cs);
+            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, cs);
+            if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, cs);
+            hipError_t he = hipStreamEndCapture(cs, &g);
             if (ce != BLP_SUCCESS) {
                 if (g) (void)hipGraphDestroy(g);
                 return ce;
@@ -652,6 +676,127 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
     h->any_box = sp.any_box;
     h->n_box = sp.n_box;
     h->solved = true;
+    return BLP_SUCCESS;
+}
+
+// ------------------------------------------------ host-resident pipeline
+blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outputs* out, int32_t chunks) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (!B || !out) return fail(h, BLP_ERR_ARG, "batch and out are required");
+    if (!out->status || !out->iters || !out->obj || !out->x || !out->y)
+        return fail(h, BLP_ERR_ARG, "all five host output buffers are required");
+    if (B->count < 0 || B->count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    const int64_t K = B->count;
+    if (K == 0) return BLP_SUCCESS;
+    if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    const bool uni = B->uniform != 0;
+    // per-LP host offsets
+    std::vector<int32_t> m(K), n(K), kind(K);
+    std::vector<int64_t> ao(K), ro(K), co(K);
+    int64_t a = 0, r = 0, c = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        m[k] = B->m[uni ? 0 : k];
+        n[k] = B->n[uni ? 0 : k];
+        kind[k] = B->kind[uni ? 0 : k];
+        if (m[k] < 0 || n[k] < 0) return fail(h, BLP_ERR_ARG, "LP %lld: negative size", (long long)k);
+        ao[k] = (!uni && B->a_off) ? B->a_off[k] : a;
+        ro[k] = (!uni && B->row_off) ? B->row_off[k] : r;
+        co[k] = (!uni && B->col_off) ? B->col_off[k] : c;
+        a += (int64_t)m[k] * n[k];
+        r += m[k];
+        c += n[k];
+    }
+    if (chunks <= 0) chunks = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, K / 1024));
+    chunks = (int32_t)std::min<int64_t>(chunks, K);
+    for (int i = 0; i < 2; ++i) {
+        if (!h->child[i]) {
+            blp_options o = h->opt;
+            o.graph = 0;
+            blp_error e = blp_create(&h->child[i], &o);
+            if (e != BLP_SUCCESS) return fail(h, e, "child handle: %s", blp_last_error(h->child[i]));
+            for (int v = 0; v < kMaxVariants; ++v) h->child[i]->remap[v] = h->remap[v];
+        }
+        if (!h->pipe[i]) HIP_TRY(h, hipStreamCreateWithFlags(&h->pipe[i], hipStreamNonBlocking));
+    }
+    struct Range { int64_t lo = INT64_MAX, hi = 0; };
+    for (int32_t ch = 0; ch < chunks; ++ch) {
+        const int64_t k0 = K * ch / chunks, k1 = K * (ch + 1) / chunks, Kc = k1 - k0;
+        const int slot = ch & 1;
+        blp_handle ch_h = h->child[slot];
+        hipStream_t s = h->pipe[slot];
+        // data ranges of this piece (offsets may be arbitrary, not packed)
+        Range ra, rr, rc;
+        for (int64_t k = k0; k < k1; ++k) {
+            ra.lo = std::min(ra.lo, ao[k]);
+            ra.hi = std::max(ra.hi, ao[k] + (int64_t)m[k] * n[k]);
+            rr.lo = std::min(rr.lo, ro[k]);
+            rr.hi = std::max(rr.hi, ro[k] + m[k]);
+            rc.lo = std::min(rc.lo, co[k]);
+            rc.hi = std::max(rc.hi, co[k] + n[k]);
+        }
+        const int64_t na = std::max<int64_t>(0, ra.hi - ra.lo), nr = std::max<int64_t>(0, rr.hi - rr.lo),
+                      nc = std::max<int64_t>(0, rc.hi - rc.lo);
+        // device layout of one piece: A | b | c | l | u (doubles) | sense (bytes)
+        const size_t in_bytes = sizeof(double) * (size_t)(na + nr + 3 * nc) + (size_t)nr + 64;
+        const size_t out_bytes = sizeof(double) * (size_t)(Kc + nc + nr) + 2 * sizeof(int32_t) * (size_t)Kc + 64;
+        // the previous piece on this stream must be done with the buffers
+        HIP_TRY(h, hipStreamSynchronize(s));
+        HIP_TRY(h, h->pin_in[slot].reserve(in_bytes));
+        HIP_TRY(h, h->pin_out[slot].reserve(out_bytes));
+        double* dA = h->pin_in[slot].as<double>();
+        double* db = dA + na;
+        double* dc = db + nr;
+        double* dl = dc + nc;
+        double* du = dl + nc;
+        int8_t* dsense = reinterpret_cast<int8_t*>(du + nc);
+        double* oobj = h->pin_out[slot].as<double>();
+        double* ox = oobj + Kc;
+        double* oy = ox + nc;
+        int32_t* ost = reinterpret_cast<int32_t*>(oy + nr);
+        int32_t* oit = ost + Kc;
+        auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+            return (src && bytes) ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+        };
+        HIP_TRY(h, up(dA, B->A ? B->A + ra.lo : nullptr, sizeof(double) * na));
+        HIP_TRY(h, up(db, B->b ? B->b + rr.lo : nullptr, sizeof(double) * nr));
+        HIP_TRY(h, up(dsense, B->sense ? B->sense + rr.lo : nullptr, (size_t)nr));
+        HIP_TRY(h, up(dc, B->c ? B->c + rc.lo : nullptr, sizeof(double) * nc));
+        HIP_TRY(h, up(dl, B->l ? B->l + rc.lo : nullptr, sizeof(double) * nc));
+        HIP_TRY(h, up(du, B->u ? B->u + rc.lo : nullptr, sizeof(double) * nc));
+        std::vector<int64_t> cao(Kc), cro(Kc), cco(Kc);
+        for (int64_t k = k0; k < k1; ++k) {
+            cao[k - k0] = ao[k] - ra.lo;
+            cro[k - k0] = ro[k] - rr.lo;
+            cco[k - k0] = co[k] - rc.lo;
+        }
+        blp_batch cb{};
+        cb.count = Kc;
+        cb.uniform = uni ? 1 : 0;
+        cb.m = uni ? m.data() : m.data() + k0;
+        cb.n = uni ? n.data() : n.data() + k0;
+        cb.kind = uni ? kind.data() : kind.data() + k0;
+        cb.a_off = cao.data();
+        cb.row_off = cro.data();
+        cb.col_off = cco.data();
+        cb.A = B->A ? dA : nullptr;
+        cb.b = B->b ? db : nullptr;
+        cb.sense = B->sense ? dsense : nullptr;
+        cb.c = B->c ? dc : nullptr;
+        cb.l = B->l ? dl : nullptr;
+        cb.u = B->u ? du : nullptr;
+        blp_outputs co_{ost, oit, oobj, ox, oy};
+        blp_error e = blp_solve_batch(ch_h, &cb, &co_, s);
+        if (e != BLP_SUCCESS) return fail(h, e, "piece %d: %s", ch, blp_last_error(ch_h));
+        // results back; x/y land at the caller's offsets
+        HIP_TRY(h, hipMemcpyAsync(out->status + k0, ost, sizeof(int32_t) * Kc, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipMemcpyAsync(out->iters + k0, oit, sizeof(int32_t) * Kc, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipMemcpyAsync(out->obj + k0, oobj, sizeof(double) * Kc, hipMemcpyDeviceToHost, s));
+        if (nc) HIP_TRY(h, hipMemcpyAsync(out->x + rc.lo, ox, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+        if (nr) HIP_TRY(h, hipMemcpyAsync(out->y + rr.lo, oy, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+    }
+    for (int i = 0; i < 2; ++i) HIP_TRY(h, hipStreamSynchronize(h->pipe[i]));
     return BLP_SUCCESS;
 }
 

@@ -148,6 +148,62 @@ __device__ __forceinline__ void price(int nslots, int lane, int id_lim, double e
     e_pos = bpos;
 }
 
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): two
+// 32x32->64 multiplies per round with the Weyl key schedule.  Used for the
+// random entering rule only.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = y0;
+        c[1] = (uint32_t)p1;
+        c[2] = y2;
+        c[3] = (uint32_t)p0;
+    }
+}
+
+// Sec. 4.2, the "random positive coefficient" rule: a uniformly random
+// nonbasic column with reduced cost above eps_price, drawn from Philox keyed
+// by the seed and addressed by (LP, pivot count).  Eligible slots are ranked
+// in slot order, so the choice is deterministic.  Every wave computes it.
+__device__ __forceinline__ void price_rpc(int nslots, int lane, int id_lim, double eps_price, uint64_t seed, int lp,
+                                          int iter, const double* s_d, const int* s_colvar, int& e_id, int& e_pos) {
+    int total = 0;
+    for (int j0 = 0; j0 < nslots; j0 += 64) {
+        const int j = j0 + lane;
+        const bool ok = j < nslots && s_colvar[j] < id_lim && s_d[j] > eps_price;
+        total += __popcll(__ballot(ok));
+    }
+    e_id = ID_NONE;
+    e_pos = -1;
+    if (total == 0) return;
+    uint32_t c[4] = {(uint32_t)iter, (uint32_t)lp, 0x52504321u, 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u = (double)((uint64_t)(c[0] >> 5) * 67108864ull + (c[1] >> 6)) * (1.0 / 9007199254740992.0);
+    int target = (int)(u * total);
+    if (target >= total) target = total - 1;
+    for (int j0 = 0; j0 < nslots; j0 += 64) {
+        const int j = j0 + lane;
+        const bool ok = j < nslots && s_colvar[j] < id_lim && s_d[j] > eps_price;
+        unsigned long long mask = __ballot(ok);
+        const int cnt = __popcll(mask);
+        if (target < cnt) {
+            for (int t = 0; t < target; ++t) mask &= mask - 1;  // drop the lowest set bits
+            const int pos = j0 + __ffsll((long long)mask) - 1;
+            e_pos = __builtin_amdgcn_readfirstlane(pos);
+            e_id = s_colvar[e_pos];
+            return;
+        }
+        target -= cnt;
+    }
+}
+
 // Step 2 (Sec. 3.1): among live rows with a pivot-column entry above
 // eps_piv, the minimum ratio rhs / entry (a row whose rhs is <= 0 offers a
 // zero step); ties to the smallest basic variable id.  Every wave computes

@@ -17,7 +17,10 @@
 namespace blp {
 
 // Dynamic LDS layout for a launch whose LPs have at most `rows` tableau rows
-// (ld, a multiple of 64) and `cols` column slots.
+// (ld, a multiple of 16, at most GM_MAX_LD) and `cols` column slots.
+// Largest leading dimension handled (rows incl. objective rows, padded to 16).
+constexpr int GM_MAX_LD = 2048;
+
 struct GmLds {
     double *d, *p, *b, *f, *sig;
     int *colvar, *basis, *artrow, *rank;
@@ -27,7 +30,8 @@ __host__ __device__ inline size_t gm_lds_bytes(int ld, int cols) {
     return (size_t)cols * (8 + 8 + 4) + (size_t)ld * (8 + 8 + 8 + 4 + 4 + 4 + 1) + 64;
 }
 
-template <int NW>
+// QM: 64-row chunks per column held by one lane (ld <= 64 QM).
+template <int NW, int QM>
 __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     constexpr int NT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -191,7 +195,10 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 e = bpos;
                 e_id = bid;
             } else {
-                price(RHS, lane, id_lim, P.eps_price, degen >= bland_after, S.d, S.colvar, e_id, e);
+                if (P.pivot_rule == 1 && degen < bland_after)
+                    price_rpc(RHS, lane, id_lim, P.eps_price, P.seed, k, iters, S.d, S.colvar, e_id, e);
+                else
+                    price(RHS, lane, id_lim, P.eps_price, degen >= bland_after, S.d, S.colvar, e_id, e);
                 if (e_id == ID_NONE) {
                     if (mode == 2) {
                         st = ST_OPTIMAL;
@@ -227,17 +234,33 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             for (int j = t; j < C; j += NT) S.p[j] = (j == e ? 1.0 : Tg[(int64_t)j * ld + l]) / pe;
             __syncthreads();
             const int act = phase == 1 ? ROW_W : ROW_OBJ;
+            // this lane's rows i = lane + 64 q and their pivot-column entries
+            double nf[QM];
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int i = lane + 64 * q;
+                nf[q] = i < ld ? -S.f[i] : 0.0;
+            }
             for (int j = wave; j < C; j += NW) {
                 double* col = Tg + (int64_t)j * ld;
                 const double pj = S.p[j];
                 const bool je = j == e;
-                for (int i = lane; i < ld; i += 64) {
-                    const double old = je ? 0.0 : col[i];
-                    double v = __builtin_fma(-S.f[i], pj, old);
-                    v = i == l ? pj : v;
-                    col[i] = v;
-                    if (i == act) S.d[j] = v;
-                    if (j == RHS) S.b[i] = v;
+                double v[QM];
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    const int i = lane + 64 * q;
+                    v[q] = (i < ld && !je) ? col[i] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    const int i = lane + 64 * q;
+                    if (i < ld) {
+                        double w = __builtin_fma(nf[q], pj, v[q]);
+                        w = i == l ? pj : w;
+                        col[i] = w;
+                        if (i == act) S.d[j] = w;
+                        if (j == RHS) S.b[i] = w;
+                    }
                 }
             }
             if (t == 0) {
@@ -257,11 +280,32 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     }
 }
 
-hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((simplex_gm_kernel<8>), dim3(grid), dim3(512), lds_bytes, s, P);
+template <int QM>
+static hipError_t launch_gm_q(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL((simplex_gm_kernel<8, QM>), dim3(grid), dim3(512), lds_bytes, s, P);
     return hipGetLastError();
 }
-const void* gm_kernel_ptr() { return reinterpret_cast<const void*>(&simplex_gm_kernel<8>); }
+static int gm_chunks(int ld) { return ld <= 64 ? 1 : ld <= 128 ? 2 : ld <= 256 ? 4 : ld <= 512 ? 8 : ld <= 1024 ? 16 : 32; }
+hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
+    switch (gm_chunks(P.ws_ld)) {
+        case 1: return launch_gm_q<1>(P, grid, lds_bytes, s);
+        case 2: return launch_gm_q<2>(P, grid, lds_bytes, s);
+        case 4: return launch_gm_q<4>(P, grid, lds_bytes, s);
+        case 8: return launch_gm_q<8>(P, grid, lds_bytes, s);
+        case 16: return launch_gm_q<16>(P, grid, lds_bytes, s);
+        default: return launch_gm_q<32>(P, grid, lds_bytes, s);
+    }
+}
+const void* gm_kernel_ptr(int ld) {
+    switch (gm_chunks(ld)) {
+        case 1: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 1>);
+        case 2: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 2>);
+        case 4: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4>);
+        case 8: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 8>);
+        case 16: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 16>);
+        default: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 32>);
+    }
+}
 int gm_threads() { return 512; }
 
 }  // namespace blp

@@ -56,7 +56,7 @@ simplex_reg_kernel(KParams P) {
     __shared__ int s_k, s_nart, s_bad;
     // Staging area for building the initial tableau, SR rows at a time
     // (row-major, CP columns), filled with coalesced loads.
-    constexpr int SR = RP < 32 ? RP : 32;
+    constexpr int SR = RP < 16 ? RP : 16;
     __shared__ double s_T[SR * CP];
 
     const int t = threadIdx.x;
@@ -100,6 +100,7 @@ simplex_reg_kernel(KParams P) {
         }
         __syncthreads();
         int bad = prep_rows<NT>(P, L, t, s_sig, s_b, s_flag);
+        for (int j = t; j < n; j += NT) s_d[j] = P.c[L.col_off + j];  // objective row source
         __syncthreads();
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
         __syncthreads();
@@ -132,21 +133,33 @@ simplex_reg_kernel(KParams P) {
         // its column block (a select keeps the tile out of divergent branches).
         for (int r0 = 0; r0 < RP; r0 += SR) {
             __syncthreads();
-            for (int e = t; e < SR * CP; e += NT) {
-                const int i = r0 + e / CP, j = e - (e / CP) * CP;
+            // all of this thread's loads of the chunk are issued before any use
+            constexpr int EPT = (SR * CP + NT - 1) / NT;
+            double av[EPT];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int e = t + q * NT;
+                const int i = r0 + e / CP, j = e % CP;
+                const bool ld = e < SR * CP && i < m && j < n;
+                av[q] = ld ? P.A[L.a_off + (int64_t)i * n + j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int e = t + q * NT;
+                if (e >= SR * CP) break;
+                const int i = r0 + e / CP, j = e % CP;
                 double v = 0.0;
                 if (i < m) {
                     if (j < n) {
-                        const double a = P.A[L.a_off + (int64_t)i * n + j];
-                        bad |= !isfinite(a);
-                        v = s_sig[i] * a;
+                        bad |= !isfinite(av[q]);
+                        v = s_sig[i] * av[q];
                     } else if (j < n + nart) {
                         v = s_artrow[j - n] == i ? -1.0 : 0.0;
                     } else if (j == COL_RHS) {
                         v = s_b[i];
                     }
                 } else if (i == ROW_OBJ) {
-                    v = j < n ? P.c[L.col_off + j] : 0.0;
+                    v = j < n ? s_d[j] : 0.0;
                 } else if (i == ROW_W && nart > 0) {
                     v = s_p[j];
                 }
@@ -302,7 +315,10 @@ simplex_reg_kernel(KParams P) {
                 e = bpos;
                 e_id = bid;
             } else {
-                price(COL_RHS, lane, id_lim, P.eps_price, degen >= bland_after, s_d, s_colvar, e_id, e);
+                if (P.pivot_rule == 1 && degen < bland_after)
+                    price_rpc(COL_RHS, lane, id_lim, P.eps_price, P.seed, k, iters, s_d, s_colvar, e_id, e);
+                else
+                    price(COL_RHS, lane, id_lim, P.eps_price, degen >= bland_after, s_d, s_colvar, e_id, e);
                 if (e_id == ID_NONE) {
                     if (mode == 2) {
                         st = ST_OPTIMAL;

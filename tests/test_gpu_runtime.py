@@ -127,3 +127,60 @@ def test_errors_from_the_device_side():
     assert st[0] == 0 and ob[0] == ref["obj"][2]
     s.close()
     s2.close()
+
+
+def test_rpc_rule_reaches_the_same_optimum():
+    """Sec. 4.2's random-positive-coefficient rule: same status and optimum as
+    the oracle (which uses the largest-coefficient rule), more pivots on
+    average, deterministic for a given seed.  The pivot path is not compared
+    (parity unpinned for the path; only the optimum is unique)."""
+    import paper_1609_08114_amd as blp
+    from solve_util import compare, crafted_batch, oracle_solve
+    for hb, tag in ((lpgen.config(1, range(1000)), "cfg1"), (lpgen.config(2, range(200)), "cfg2"),
+                    (lpgen.config(4, range(60)), "cfg4")):
+        o = oracle_solve(hb)
+        r1 = gpu_solve(hb, pivot_rule=blp.BLP_RULE_RPC, seed=11)
+        compare(hb, r1, o, strict=False, tag="rpc-" + tag)
+        r2 = gpu_solve(hb, pivot_rule=blp.BLP_RULE_RPC, seed=11)
+        assert np.array_equal(_bits(r1["obj"]), _bits(r2["obj"])) and np.array_equal(r1["iters"], r2["iters"])
+        if tag == "cfg2":
+            assert r1["iters"].mean() > o["iters"].mean()
+            r3 = gpu_solve(hb, pivot_rule=blp.BLP_RULE_RPC, seed=12)
+            assert not np.array_equal(r1["iters"], r3["iters"])
+    rng = np.random.default_rng(17)
+    lps = []
+    for _ in range(300):
+        m = int(rng.integers(1, 6))
+        n = int(rng.integers(1, 4))
+        lps.append(dict(A=rng.integers(-3, 7, size=(m, n)).astype(float), b=rng.integers(-4, 11, size=m).astype(float),
+                        c=rng.integers(-2, 6, size=n).astype(float), sense=rng.integers(0, 2, size=m).astype(np.int8)))
+    hb = crafted_batch(lps)
+    compare(hb, gpu_solve(hb, pivot_rule=blp.BLP_RULE_RPC, seed=5), oracle_solve(hb), strict=False, tag="rpc-small")
+
+
+@pytest.mark.parametrize("chunks", [1, 3, 0])
+def test_host_resident_pipeline(chunks):
+    """Host arrays in, host results out, pieces on two streams: identical to
+    the device-resident solve."""
+    import ctypes
+
+    import paper_1609_08114_amd as blp
+    hb = lpgen.config(4, range(4000, 4150))
+    ref = gpu_solve(hb)
+    s = blp.Solver()
+    K = hb.count
+    st = np.zeros(K, np.int32)
+    it = np.zeros(K, np.int32)
+    ob = np.zeros(K)
+    x = np.zeros(hb.c.size)
+    y = np.zeros(max(1, hb.b.size))
+    keep = [np.ascontiguousarray(a) for a in (hb.m, hb.n, hb.kind, hb.a_off, hb.row_off, hb.col_off)]
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    b = blp.blp_batch(K, 0, 0, *[P(a) for a in keep], P(hb.A), P(hb.b), P(hb.sense), P(hb.c), P(hb.l), P(hb.u))
+    o = blp.blp_outputs(P(st), P(it), P(ob), P(x), P(y))
+    blp.blp_solve_batch_host(s.h, b, o, chunks)
+    s.close()
+    assert np.array_equal(st, ref["status"]) and np.array_equal(it, ref["iters"])
+    assert np.array_equal(_bits(ob), _bits(ref["obj"]))
+    assert np.array_equal(_bits(x), _bits(ref["x"][:x.size]))
+    assert np.array_equal(_bits(y[:hb.b.size]), _bits(ref["y"][:hb.b.size]))
