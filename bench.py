@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+METRIC = "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr\u22641e-9"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_simplex_reg_100x100.json")
 KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_common.hpp",
                   "paper_1609_08114_amd/csrc/blp_kernels.hpp", "paper_1609_08114_amd/csrc/variants.hpp"]
@@ -78,9 +79,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=50_000)
     ap.add_argument("--one-per-launch-sample", type=int, default=2_000)
-    ap.add_argument("--cpu-sample", type=int, default=20_000)
+    ap.add_argument("--cpu-sample", type=int, default=50_000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classes", action="store_true")
+    ap.add_argument("--no-host", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="only a 1 GiB device copy followed by one persistent solve of the batch "
+                         "(the workload of the HBM-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch shards across GPUs "
@@ -92,6 +98,10 @@ def main():
     import lpgen
     import paper_1609_08114_amd as blp
     assert torch.cuda.is_available(), "needs a GPU"
+
+    if args.counter_pass:
+        counter_pass(blp, torch, lpgen, args.batch)
+        return
 
     # ------------------------------------------------------------ main line
     K = args.batch
@@ -114,9 +124,12 @@ def main():
     dom = int(np.argmax(kms))
     dom_ms = float(kms[dom])
     m = n = 100
-    # condensed tableau of a type-1 LP: (m + 1) rows x (n + 1) columns; one
-    # pivot = one FMA per entry
-    flops = float(iters.sum()) * 2.0 * (m + 1) * (n + 1)
+    # Work per pivot as the method states it: the full tableau of a type-1
+    # LP has (m + 1) rows and (n + m + 1) columns, one FMA per entry.  The
+    # kernel holds only the n nonbasic columns and the rhs (the basic
+    # columns are unit vectors), so it executes (m + 1)(n + 1) of them.
+    flops = float(iters.sum()) * 2.0 * (m + 1) * (n + m + 1)
+    executed = float(iters.sum()) * 2.0 * (m + 1) * (n + 1)
     achieved = flops / (dom_ms / 1e3) / 1e12
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -127,7 +140,9 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "kernel": names[dom], "kernel_ms": round(dom_ms, 4),
-                "algorithmic_flops": flops, "pivots": int(iters.sum()),
+                "algorithmic_flops": flops, "executed_flops": executed,
+                "executed_frac": round(executed / (dom_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                "pivots": int(iters.sum()),
                 "hbm_input_bytes": input_bytes,
                 "hbm_frac_of_input_read": round(input_bytes / (dom_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 
@@ -139,6 +154,13 @@ def main():
     rate1 = S / (ms1 / 1e3)
     assert np.array_equal(out1["obj"][:S].cpu().numpy().view(np.int64), obj[:S].view(np.int64))
     log(f"one-per-launch: {rate1:,.0f} LPs/s")
+
+    # --------------------------------- end to end from pinned host memory
+    host = None
+    if not args.no_host:
+        log("end to end from pinned host memory")
+        host = rate_host_resident(blp, torch, hb, obj)
+        log(f"host-resident: {host}")
 
     # -------------------------------------------------- other size classes
     per_class = {}
@@ -154,12 +176,16 @@ def main():
         ids = np.arange(C)
         sample = lpgen.config(2, ids)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        log(f"CPU oracle on {C} LPs, {cores} threads")
-        t = time.perf_counter()
-        ref = oracle.solve_batch(sample)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(C / dt, 1), "unit": "LPs/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {C} LPs of the 50,000-LP batch (type 1, m=n=100), OpenMP one LP per thread",
+        log(f"CPU oracle on {C} LPs, {cores} threads, repeated for about {args.cpu_seconds:.0f} s")
+        reps, dt = 0, 0.0
+        while reps < 1 or (dt < args.cpu_seconds and reps < 50):
+            t = time.perf_counter()
+            ref = oracle.solve_batch(sample)
+            dt += time.perf_counter() - t
+            reps += 1
+        cpu = {"value": round(C * reps / dt, 1), "unit": "LPs/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {C} LPs of the 50,000-LP batch (type 1, m=n=100) solved {reps} times, "
+                         "OpenMP one LP per thread",
                "seconds": round(dt, 3)}
         rel = np.abs(obj[:C] - ref["obj"]) / np.maximum(1.0, np.abs(ref["obj"]))
         parity = {"checked": C, "status_mismatch": int((status[:C] != ref["status"]).sum()),
@@ -169,13 +195,14 @@ def main():
         log(f"oracle: {cpu['value']:,.0f} LPs/s; parity {parity}")
 
     line = {
-        "metric": "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr<=1e-9",
+        "metric": METRIC,
         "value": round(value, 1), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "type-1 dense LPs, m=n=100 (tableau 101x101 condensed, 101x201 full), "
                                "A~U(1,10) b~U(10,100) c~U(1,10), seed 1002",
                    "batch": K, "m": 100, "n": 100, "mode": "persistent"},
+        "end_to_end_pinned_host": host,
         "one_per_launch": {"value": round(rate1, 1), "unit": "LPs/s", "sample": f"first {S} LPs",
                            "speedup_persistent": round(value / rate1, 2)},
         "statuses": np.bincount(status, minlength=5).tolist(),
@@ -188,6 +215,56 @@ def main():
         "per_class": per_class,
     }
     print(json.dumps(line), flush=True)
+
+
+def rate_host_resident(blp, torch, hb, ref_obj, steps=3):
+    """LPs/s including the PCIe copies: inputs in pinned host memory, results
+    back in pinned host memory, pieces alternating on two streams."""
+    import ctypes
+    K = hb.count
+
+    def pinned(a):
+        t = torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+        return t
+
+    keep = [pinned(a) for a in (hb.m, hb.n, hb.kind, hb.a_off, hb.row_off, hb.col_off, hb.A, hb.b, hb.sense,
+                                hb.c, hb.l, hb.u)]
+    outs = [torch.empty(K, dtype=torch.int32).pin_memory(), torch.empty(K, dtype=torch.int32).pin_memory(),
+            torch.empty(K, dtype=torch.float64).pin_memory(), torch.empty(hb.c.size, dtype=torch.float64).pin_memory(),
+            torch.empty(max(1, hb.b.size), dtype=torch.float64).pin_memory()]
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    b = blp.blp_batch(K, 0, 0, *[P(t) for t in keep])
+    o = blp.blp_outputs(*[P(t) for t in outs])
+    s = blp.Solver()
+    blp.blp_solve_batch_host(s.h, b, o, 0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        blp.blp_solve_batch_host(s.h, b, o, 0)
+    dt = (time.perf_counter() - t0) / steps
+    s.close()
+    same = bool(np.array_equal(outs[2].numpy().view(np.int64), ref_obj.view(np.int64)))
+    in_bytes = sum(t.numel() * t.element_size() for t in keep)
+    out_bytes = sum(t.numel() * t.element_size() for t in outs)
+    return {"value": round(K / dt, 1), "unit": "LPs/s", "ms": round(dt * 1e3, 3), "pcie_bytes": in_bytes + out_bytes,
+            "obj_identical_to_resident": same}
+
+
+def counter_pass(blp, torch, lpgen, K):
+    """The workload of the HBM byte-counter runs: one plain device copy of
+    1 GiB (the calibration of FETCH_SIZE/WRITE_SIZE) and one persistent solve
+    of the K-LP batch."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    hb = lpgen.config(2, range(K))
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver()
+    s.solve(db)
+    torch.cuda.synchronize()
+    s.close()
+    log(f"counter pass done: copy of {src.numel() * 8} bytes, one solve of {K} LPs")
 
 
 def bench_classes(blp, torch, lpgen) -> dict:
