@@ -283,10 +283,17 @@ def bench_classes(blp, torch, lpgen) -> dict:
         log(f"class {name}: {n_batch} LPs")
         hb = lpgen.config(cfg, range(n_batch), part=part) if part else lpgen.config(cfg, range(n_batch))
         db = blp.DeviceBatch.from_host(hb)
-        ms, _, out, _ = time_solver(blp, torch, db, 3, 1)
+        ms, kms, out, _ = time_solver(blp, torch, db, 3, 1)
         st = np.bincount(out["status"][:n_batch].cpu().numpy(), minlength=5).tolist()
         entry = {"lps": n_batch, "persistent_lps_per_s": round(n_batch / (ms / 1e3), 1), "ms": round(ms, 3),
                  "statuses": st}
+        if part and part.startswith("box"):
+            # Eq. (7) is a stream: read c, l, u, write x, obj, status, iters
+            n = int(hb.n[0])
+            kb = float(kms[-2])
+            byt = n_batch * (24.0 * n + 8.0 * n + 16.0)
+            entry.update({"kernel_ms": round(kb, 4), "hbm_bytes": byt, "hbm_GBps": round(byt / kb / 1e6, 1),
+                          "hbm_frac": round(byt / kb / 1e6 / PEAK_HBM_GBS, 4)})
         if n_single:
             sub = lpgen.config(cfg, range(n_single), part=part) if part else lpgen.config(cfg, range(n_single))
             sdb = blp.DeviceBatch.from_host(sub)

@@ -139,6 +139,88 @@ __global__ void hyperbox_kernel(KParams P) {
     }
 }
 
+// Eq. (7) for a uniform batch of n-variable boxes laid out back to back:
+// one wave per group of 64 LPs.  c, l, u are read with consecutive lanes on
+// consecutive doubles and x is written the same way; c and h go through LDS
+// (rows padded to n + 1 doubles against bank conflicts) so that lane i can
+// sum LP i's products in increasing order, as the per-LP kernel does.
+// Invalid-data flags are OR-ed per LP in LDS.
+__global__ void __launch_bounds__(64) hyperbox_tile_kernel(KParams P) {
+    extern __shared__ double s_mem[];
+    const int N = P.un, NP = N + 1;
+    double* s_c = s_mem;
+    double* s_h = s_mem + 64 * NP;
+    int* s_fl = reinterpret_cast<int*>(s_h + 64 * NP);
+    const int lane = threadIdx.x;
+    const int64_t K = P.count;
+    constexpr int UNR = 8;
+    for (int64_t g = blockIdx.x; g * 64 < K; g += gridDim.x) {
+        const int64_t k0 = g * 64;
+        const int nl = (int)(K - k0 < 64 ? K - k0 : 64);
+        const int64_t e0 = k0 * N;
+        const int ne = nl * N;
+        s_fl[lane] = 0;
+        __syncthreads();
+        for (int eb = 0; eb < ne; eb += 64 * UNR) {
+            double cv[UNR], lv[UNR], uv[UNR];
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int e = eb + q * 64 + lane;
+                const int64_t a = e0 + (e < ne ? e : 0);
+                cv[q] = P.c[a];
+                lv[q] = P.l[a];
+                uv[q] = P.u[a];
+            }
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int e = eb + q * 64 + lane;
+                if (e < ne) {
+                    const double h = cv[q] < 0.0 ? lv[q] : uv[q];
+                    P.x[e0 + e] = h;
+                    const int lk = e / N, i = e - lk * N;
+                    s_c[lk * NP + i] = cv[q];
+                    s_h[lk * NP + i] = h;
+                    const int f = ((!isfinite(cv[q]) || !isfinite(lv[q]) || !isfinite(uv[q])) ? 1 : 0) |
+                                  (lv[q] > uv[q] ? 2 : 0);
+                    if (f) atomicOr(&s_fl[lk], f);
+                }
+            }
+        }
+        __syncthreads();
+        if (lane < nl) {
+            double acc = 0.0;
+            for (int i = 0; i < N; ++i) acc = __builtin_fma(s_c[lane * NP + i], s_h[lane * NP + i], acc);
+            const int f = s_fl[lane];
+            const bool bad = f & 1, empty = f & 2;
+            const int64_t k = k0 + lane;
+            if (bad) {
+                __threadfence();  // after this wave's x = h stores
+                for (int i = 0; i < N; ++i) P.x[e0 + (int64_t)lane * N + i] = __builtin_nan("");
+            }
+            P.status[k] = bad ? ST_NUMERICAL : (empty ? ST_INFEASIBLE : ST_OPTIMAL);
+            P.iters[k] = 0;
+            P.obj[k] = bad ? __builtin_nan("") : (empty ? -__builtin_inf() : acc);
+        }
+        __syncthreads();
+    }
+}
+
+// Adjoint of a uniform hyperbox batch, one thread per variable.
+__global__ void __launch_bounds__(256) backward_hyperbox_flat_kernel(KParams P, const double* g, double* dc,
+                                                                      double* dl, double* du) {
+    const int N = P.un;
+    const int64_t E = P.count * (int64_t)N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / N;
+        const bool ok = P.status[k] == ST_OPTIMAL;
+        const double gk = ok ? g[k] : 0.0;
+        const double ci = P.c[e];
+        if (dc) dc[e] = ok ? gk * P.x[e] : 0.0;
+        if (dl) dl[e] = ok && ci < 0.0 ? gk * ci : 0.0;
+        if (du) du[e] = ok && !(ci < 0.0) ? gk * ci : 0.0;
+    }
+}
+
 // Adjoint for simplex LPs: dc = g x*, db = g y*, dA = -g y* x*^T.  One
 // workgroup per LP; LPs not OPTIMAL get zeros.
 __global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const double* g, double* dc, double* db,
@@ -215,6 +297,11 @@ static unsigned grid_for(int64_t items, int per_block, int64_t cap) {
     return (unsigned)b;
 }
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s) {
+    if (P.uniform && !P.list && P.un >= 1 && P.un <= kBoxTileMaxN) {
+        const size_t lds = sizeof(double) * 2 * 64 * (size_t)(P.un + 1) + sizeof(int) * 64;
+        hipLaunchKernelGGL(hyperbox_tile_kernel, dim3(grid_for(P.count, 64, 1 << 15)), dim3(64), lds, s, P);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
@@ -226,6 +313,11 @@ hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc
 }
 hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
                                     double* du, hipStream_t s) {
+    if (P.uniform && !P.list && P.un >= 1) {
+        hipLaunchKernelGGL(backward_hyperbox_flat_kernel, dim3(grid_for(P.count * (int64_t)P.un, 256, 1 << 16)),
+                           dim3(256), 0, s, P, g, dc, dl, du);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(backward_hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P, g,
                        dc, dl, du);
     return hipGetLastError();

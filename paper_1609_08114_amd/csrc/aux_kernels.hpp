@@ -9,6 +9,9 @@
 namespace blp {
 
 constexpr int kMaxVariants = 24;
+// Widest uniform hyperbox served by the LDS-transposing kernel (LDS per wave:
+// 2 * 64 * (n + 1) doubles).
+constexpr int kBoxTileMaxN = 48;
 
 // Register-tile variant shapes handed to the classify kernel.
 struct VariantTable {

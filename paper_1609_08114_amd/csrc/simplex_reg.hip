@@ -24,6 +24,7 @@
 // the pivot element (Step 3's NewPivotRow) -> barrier -> register update and
 // mirrors -> barrier.
 #include "blp_kernels.hpp"
+#include "simplex_blk.hpp"
 #include "simplex_common.hpp"
 #include "variants.hpp"
 
@@ -56,7 +57,7 @@ simplex_reg_kernel(KParams P) {
     __shared__ int s_k, s_nart, s_bad;
     // Staging area for building the initial tableau, SR rows at a time
     // (row-major, CP columns), filled with coalesced loads.
-    constexpr int SR = RP < 16 ? RP : 16;
+    constexpr int SR = RP < 32 ? RP : 32;
     __shared__ double s_T[SR * CP];
 
     const int t = threadIdx.x;
@@ -389,6 +390,19 @@ static const void* kernel_ptr() {
     return reinterpret_cast<const void*>(&simplex_reg_kernel<NW, TC, CT, WPE>);
 }
 
+template <int NW, int GC, int RB, int CB, int WPE>
+static hipError_t launch_blk(const KParams& P, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((simplex_blk_kernel<NW, GC, RB, CB, WPE>), dim3(grid), dim3(NW * 64), 0, s, P);
+    return hipGetLastError();
+}
+template <int NW, int GC, int RB, int CB, int WPE>
+static const void* kernel_ptr_blk() {
+    return reinterpret_cast<const void*>(&simplex_blk_kernel<NW, GC, RB, CB, WPE>);
+}
+
+#define BLP_BLK_VARIANT(NAME, NW, GC, RB, CB, WPE)                                                    \
+    {NAME, (NW) * 64, (NW) * 64 / (GC) * (RB), (GC) * (CB), &launch_blk<NW, GC, RB, CB, WPE>, \
+     &kernel_ptr_blk<NW, GC, RB, CB, WPE>},
 #define BLP_REG_VARIANT(NAME, NW, TC, CT, WPE) \
     {NAME, (NW) * 64, (NW) * 64 / (TC), (TC) * (CT), &launch_reg<NW, TC, CT, WPE>, &kernel_ptr<NW, TC, CT, WPE>},
 

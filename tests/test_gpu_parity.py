@@ -133,6 +133,56 @@ def test_every_kernel_variant_identical():
             assert np.array_equal(ref[k].view(np.int64), g[k].view(np.int64)), (v, k)
 
 
+def _crafted_lps():
+    A, b, c = pins.klee_minty(7)
+    beale = dict(A=[[0.25, -8.0, -1.0, 9.0], [0.5, -12.0, -0.5, 3.0], [0.0, 0.0, 1.0, 0.0]], b=[0, 0, 1],
+                 c=[0.75, -20.0, 0.5, -6.0])
+    lps = [
+        dict(A=[[1, 1], [1, 1]], b=[1, 2], c=[1, 1], sense=[0, 1]),
+        dict(A=[[1, 1]], b=[-1], c=[1, 1]),
+        dict(A=[[1, -1]], b=[1], c=[1, 0]),
+        dict(A=[[1, 1]], b=[2], c=[1, 0], sense=[1]),
+        dict(A=[[1, 2], [3, 1]], b=[4, 5], c=[-1, -2]),
+        dict(A=[[1, 1], [1, 1], [1, 1]], b=[2, 2, 2], c=[1, 2], sense=[1, 1, 0]),
+        dict(A=[[1, 1, 0], [1, 1, 0], [0, 1, 1], [0, 1, 1]], b=[3, 3, 2, 2], c=[1, 2, 1], sense=[1, 1, 1, 0]),
+        dict(A=[[1.0, -1.0], [-1.0, 1.0], [1.0, 1.0]], b=[0, 0, 4], c=[1, 1]),
+        beale,
+        dict(A=A, b=b, c=c),
+    ]
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        m = int(rng.integers(1, 7))
+        n = int(rng.integers(1, 5))
+        lps.append(dict(A=rng.integers(-3, 7, size=(m, n)).astype(float), b=rng.integers(-4, 11, size=m).astype(float),
+                        c=rng.integers(-2, 6, size=n).astype(float), sense=rng.integers(0, 2, size=m).astype(np.int8)))
+    # redundant equality-like pairs: a >= row and a <= row with the same data
+    for _ in range(60):
+        m = int(rng.integers(2, 6))
+        n = int(rng.integers(2, 5))
+        A = rng.integers(1, 5, size=(m, n)).astype(float)
+        b = rng.integers(2, 9, size=m).astype(float)
+        A = np.vstack([A, A[:1]])
+        b = np.concatenate([b, b[:1]])
+        sense = np.zeros(m + 1, np.int8)
+        sense[0] = 1
+        lps.append(dict(A=A, b=b, c=rng.integers(-1, 5, size=n).astype(float), sense=sense))
+    return lps
+
+
+def test_every_variant_on_crafted_and_degenerate():
+    """Each register-tile variant, forced, on the crafted statuses, dead rows
+    after phase 1, degenerate and cycling LPs: identical bits to the oracle's
+    strict comparison."""
+    import paper_1609_08114_amd as blp
+    hb = crafted_batch(_crafted_lps())
+    o = oracle_solve(hb)
+    assert set(np.unique(o["status"])) >= {0, 1, 2}
+    for v in range(len(blp.variants())):
+        print(f"[parity] crafted variant {v}", flush=True)
+        g = gpu_solve(hb, variant=v)
+        compare(hb, g, o, strict=True, tag=f"crafted-v{v}")
+
+
 def test_ragged_and_empty():
     # LPs of every size class in one batch, not in order, plus zero-size batch
     rng = np.random.default_rng(3)
