@@ -167,6 +167,16 @@ def main():
     if not args.no_classes:
         per_class = bench_classes(blp, torch, lpgen)
 
+    # ---------------------- shared constraints, many objectives (Sec. 7)
+    shared = None
+    if not args.no_classes:
+        shared = bench_shared(blp, torch, lpgen, oracle_check=not args.no_cpu)
+
+    # ------------------------------------------- layout ablation (Sec. 4.3)
+    ablation = None
+    if not args.no_classes:
+        ablation = layout_ablation(blp, torch, lpgen)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     parity = None
@@ -213,6 +223,8 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "per_class": per_class,
+        "layout_ablation": ablation,
+        "shared_constraints": shared,
     }
     print(json.dumps(line), flush=True)
 
@@ -265,6 +277,95 @@ def counter_pass(blp, torch, lpgen, K):
     torch.cuda.synchronize()
     s.close()
     log(f"counter pass done: copy of {src.numel() * 8} bytes, one solve of {K} LPs")
+
+
+def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:
+    """One workload-2 polytope (m = n = 100) queried in K directions, as in
+    support-function sampling: directions swept around a circle, and random
+    unit directions.  blp_solve_shared (phase 1 once, warm starts) against
+    the same K LPs solved independently by blp_solve_batch."""
+    dev = torch.device("cuda")
+    lp = lpgen.config(2, [0]).lp(0)
+    A, b, sense = lp["A"], lp["b"], lp["sense"]
+    m, n = A.shape
+    rng = np.random.default_rng(1007)
+    u, v = rng.normal(size=(2, n))
+    t = np.linspace(0.0, 2.0 * np.pi, K, endpoint=False)
+    sweep = np.cos(t)[:, None] * u + np.sin(t)[:, None] * v
+    G = rng.normal(size=(K, n))
+    rand = G / np.linalg.norm(G, axis=1, keepdims=True)
+    Ad = torch.from_numpy(np.ascontiguousarray(A).ravel()).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    sd = torch.from_numpy(sense).to(dev)
+    res = {"polytope": "workload-2 LP 0, m=n=100", "lps": K}
+    for name, C in (("circle_sweep", sweep), ("random_directions", rand)):
+        Cd = torch.from_numpy(np.ascontiguousarray(C)).to(dev)
+        s = blp.Solver()
+        out = s.solve_shared(Ad, bd, sd, Cd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            out = s.solve_shared(Ad, bd, sd, Cd)
+        torch.cuda.synchronize()
+        ms_sh = (time.perf_counter() - t0) * 1e3 / reps
+        s.close()
+        obj_sh = out["obj"][:K].cpu().numpy()
+        it_sh = out["iters"][:K].cpu().numpy()
+        st_sh = out["status"][:K].cpu().numpy()
+        # the same LPs, independently
+        hb = lpgen.make_batch(1002, np.zeros(K, np.int64), np.ones(K, np.int32), np.full(K, m), np.full(K, n))
+        hb.A = np.tile(A.ravel(), K)
+        hb.b = np.tile(b, K)
+        hb.sense = np.tile(sense, K)
+        hb.c = np.ascontiguousarray(C).ravel()
+        db = blp.DeviceBatch.from_host(hb)
+        ms_ind, _, out_i, _ = time_solver(blp, torch, db, 3, 1)
+        obj_i = out_i["obj"][:K].cpu().numpy()
+        st_i = out_i["status"][:K].cpu().numpy()
+        it_i = out_i["iters"][:K].cpu().numpy()
+        del db
+        ok = st_i == 0
+        rel = np.abs(obj_sh[ok] - obj_i[ok]) / np.maximum(1.0, np.abs(obj_i[ok]))
+        entry = {"shared_lps_per_s": round(K / (ms_sh / 1e3), 1), "shared_ms": round(ms_sh, 3),
+                 "independent_lps_per_s": round(K / (ms_ind / 1e3), 1), "independent_ms": round(ms_ind, 3),
+                 "speedup": round(ms_ind / ms_sh, 2), "pivots_per_lp_shared": round(float(it_sh.mean()), 2),
+                 "pivots_per_lp_independent": round(float(it_i.mean()), 2),
+                 "status_mismatch": int((st_sh != st_i).sum()), "max_obj_relerr_vs_independent": float(rel.max())}
+        if oracle_check:
+            import oracle
+            S = 2000
+            sub = lpgen.make_batch(1002, np.zeros(S, np.int64), np.ones(S, np.int32), np.full(S, m), np.full(S, n))
+            sub.A, sub.b, sub.sense = hb.A[:S * m * n], hb.b[:S * m], hb.sense[:S * m]
+            sub.c = hb.c[:S * n]
+            ref = oracle.solve_batch(sub)
+            okr = ref["status"] == 0
+            relo = np.abs(obj_sh[:S][okr] - ref["obj"][okr]) / np.maximum(1.0, np.abs(ref["obj"][okr]))
+            entry["oracle_sample"] = S
+            entry["oracle_status_mismatch"] = int((st_sh[:S] != ref["status"]).sum())
+            entry["oracle_max_obj_relerr"] = float(relo.max())
+        res[name] = entry
+        log(f"shared {name}: {entry}")
+    return res
+
+
+def layout_ablation(blp, torch, lpgen, K=512) -> dict:
+    """The streaming kernel on workload 3 (type-2 LPs, m = n = 200, tableau
+    202 x 301 in HBM) with the coalesced column-major workspace against the
+    row-major one under the same thread mapping (Sec. 4.3's comparison)."""
+    hb = lpgen.config(3, range(K))
+    db = blp.DeviceBatch.from_host(hb)
+    res = {"lps": K, "workload": "type-2 m=n=200, streaming kernel"}
+    objs = {}
+    for name, lay in (("column_major", blp.BLP_LAYOUT_COLUMN), ("row_major", blp.BLP_LAYOUT_ROW)):
+        log(f"layout ablation: {name}")
+        ms, kms, out, _ = time_solver(blp, torch, db, 1, 1, variant=-2, layout=lay)
+        res[name] = {"ms": round(ms, 3), "lps_per_s": round(K / (ms / 1e3), 1),
+                     "kernel_ms": round(float(kms[len(blp.variants())]), 3)}
+        objs[name] = out["obj"][:K].cpu().numpy().view(np.int64)
+    res["row_over_column"] = round(res["row_major"]["kernel_ms"] / res["column_major"]["kernel_ms"], 2)
+    res["bit_identical"] = bool(np.array_equal(objs["column_major"], objs["row_major"]))
+    return res
 
 
 def bench_classes(blp, torch, lpgen) -> dict:

@@ -93,9 +93,15 @@ typedef struct {
     int32_t graph;         /* nonzero (persistent mode): capture the launch sequence into a hipGraph
                               per batch signature and replay it when the same batch recurs */
     int32_t pivot_rule;    /* BLP_RULE_LPC (default) or BLP_RULE_RPC */
-    int32_t reserved_;
+    int32_t layout;        /* streaming kernel's workspace: BLP_LAYOUT_COLUMN (default, the coalesced
+                              layout of Sec. 4.3) or BLP_LAYOUT_ROW (same thread mapping on a row-major
+                              tableau: the non-coalesced access of Sec. 4.3's comparison).  Results are
+                              bit-identical; only speed differs */
     uint64_t seed;         /* RPC only: Philox4x32-10 key; draw = (seed, LP index, pivot count) */
 } blp_options;
+
+/* Workspace layouts of the streaming kernel (Sec. 4.3). */
+enum { BLP_LAYOUT_COLUMN = 0, BLP_LAYOUT_ROW = 1 };
 
 /* Entering rules (Sec. 4.2).  LPC: largest positive reduced cost (Dantzig),
  * lowest variable index on ties.  RPC: a uniformly random column among those
@@ -175,6 +181,26 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* batch, const blp_output
  * Synchronous: returns when every result is in host memory.  Afterwards
  * blp_get_solution* and blp_backward refer to the last piece only. */
 blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_outputs* out, int32_t chunks);
+
+/* Shared constraints, many objectives: maximise c_k.x subject to the same rows
+ * A x (<= | >=) b and x >= 0, for k = 0..count-1 -- the support-function
+ * sampling of Sec. 7, where one polytope is queried in many directions.
+ * A (m x n, row-major), b (m), sense (m) and C (count x n, row-major) are
+ * device pointers; out->status/iters/obj have count entries, out->x count x n
+ * (x of LP k at k*n), out->y count x m (at k*m); all device, caller-owned
+ * (C and out may be NULL when count is 0).
+ * Each workgroup runs phase 1 once and starts every further objective from
+ * the previous optimal basis (only the objective row is rebuilt), so iteration
+ * counts and, at degenerate optima, x and y may differ from independent
+ * solves; statuses and optima do not.  Needs m + 2 <= 112 and
+ * n + n_art + 1 <= 112 (n_art = rows whose "<=" form has a negative rhs),
+ * else BLP_ERR_TOO_LARGE.  Reads b and sense back to the host once
+ * (synchronising the stream); the solve itself is ordered on the stream.
+ * The handle keeps no results of this call (blp_backward and
+ * blp_get_solution refer to the last blp_solve_batch). */
+blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
+                           const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,
+                           void* hip_stream);
 
 /* Copy LP k's results of the last solve to HOST memory (synchronises the
  * solve's stream).  x (length n) and y (length m) may be NULL. */

@@ -23,13 +23,14 @@ BLP_OPTIMAL, BLP_INFEASIBLE, BLP_UNBOUNDED, BLP_ITER_LIMIT, BLP_NUMERICAL = rang
 BLP_SUCCESS, BLP_ERR_ARG, BLP_ERR_NOMEM, BLP_ERR_HIP, BLP_ERR_STATE, BLP_ERR_TOO_LARGE = range(6)
 BLP_MODE_PERSISTENT, BLP_MODE_GRID, BLP_MODE_ONE_PER_LAUNCH = range(3)
 BLP_RULE_LPC, BLP_RULE_RPC = range(2)
+BLP_LAYOUT_COLUMN, BLP_LAYOUT_ROW = range(2)
 ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_STATE", 5: "ERR_TOO_LARGE"}
 
 # Every entry point that include/blp.h declares.
 EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
            "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning",
-           "blp_solve_batch_host"]
+           "blp_solve_batch_host", "blp_solve_shared"]
 
 
 class blp_options(ctypes.Structure):
@@ -37,7 +38,7 @@ class blp_options(ctypes.Structure):
                 ("bland_after", ctypes.c_int32), ("eps_price", ctypes.c_double), ("eps_piv", ctypes.c_double),
                 ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("graph", ctypes.c_int32), ("pivot_rule", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("layout", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class blp_batch(ctypes.Structure):
@@ -90,6 +91,7 @@ def lib() -> ctypes.CDLL:
         L.blp_load_tuning.argtypes = [vp, ctypes.c_char_p]
         L.blp_tuning.argtypes = [vp, vp, P(i32)]
         L.blp_solve_batch_host.argtypes = [vp, P(blp_batch), P(blp_outputs), i32]
+        L.blp_solve_shared.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp, P(blp_outputs), vp]
         for f in EXPORTS:
             if f not in ("blp_abi_version", "blp_destroy", "blp_last_error"):
                 getattr(L, f).restype = ctypes.c_int
@@ -131,6 +133,11 @@ def blp_solve_batch(h, batch: blp_batch, out: blp_outputs | None = None, stream:
 
 def blp_solve_batch_host(h, batch: blp_batch, out: blp_outputs, chunks: int = 0) -> None:
     _check(h, lib().blp_solve_batch_host(h, ctypes.byref(batch), ctypes.byref(out), chunks))
+
+
+def blp_solve_shared(h, m: int, n: int, A, b, sense, count: int, C, out: blp_outputs,
+                     stream: int | None = None) -> None:
+    _check(h, lib().blp_solve_shared(h, m, n, A, b, sense, count, C, ctypes.byref(out), stream))
 
 
 def blp_get_solution(h, k: int, status=None, obj=None, x=None, y=None, iters=None) -> None:
@@ -266,12 +273,12 @@ class Solver:
 
     def __init__(self, device: int = 0, mode: int = BLP_MODE_PERSISTENT, variant: int = -1, max_iter: int = 0,
                  workers_per_cu: int = 0, bland_after: int = 0, profile: bool = False, graph: bool = False,
-                 pivot_rule: int = BLP_RULE_LPC, seed: int = 0):
+                 pivot_rule: int = BLP_RULE_LPC, seed: int = 0, layout: int = BLP_LAYOUT_COLUMN):
         o = blp_options_default()
         o.device, o.mode, o.variant, o.max_iter = device, mode, variant, max_iter
         o.workers_per_cu, o.bland_after, o.profile = workers_per_cu, bland_after, 1 if profile else 0
         o.graph = 1 if graph else 0
-        o.pivot_rule, o.seed = pivot_rule, seed
+        o.pivot_rule, o.seed, o.layout = pivot_rule, seed, layout
         self.device = device
         self.h = blp_create(o)
 
@@ -306,6 +313,24 @@ class Solver:
         blp_solve_batch(self.h, self._batch, o, st.cuda_stream)
         self._last = (db, outputs)
         return outputs
+
+    def solve_shared(self, A, b, sense, C, stream=None) -> dict:
+        """One constraint set (A: m x n, b, sense: m; device tensors) with the
+        objectives in the rows of C (count x n).  Returns device tensors
+        status, iters, obj (count), x (count x n), y (count x m)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        m, n = int(b.numel()), int(C.shape[1])
+        K = int(C.shape[0])
+        out = {"status": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+               "iters": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+               "obj": torch.empty(max(K, 1), dtype=torch.float64, device=dev),
+               "x": torch.empty(max(K * n, 1), dtype=torch.float64, device=dev),
+               "y": torch.empty(max(K * m, 1), dtype=torch.float64, device=dev)}
+        o = blp_outputs(*[_ptr(out[k]) for k in ("status", "iters", "obj", "x", "y")])
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        blp_solve_shared(self.h, m, n, _ptr(A), _ptr(b), _ptr(sense), K, _ptr(C), o, st.cuda_stream)
+        return out
 
     def autotune(self, db: DeviceBatch, sample: int = 512, cache_path: str | None = None, stream=None) -> None:
         import torch

@@ -34,6 +34,12 @@ hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc
 hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
                                     double* du, hipStream_t s);
 
+// Shared-constraint kernel (simplex_reg.hip): tableau shape and launcher.
+hipError_t launch_shared(const KParams& P, int grid, hipStream_t s);
+const void* shared_kernel_ptr();
+int shared_threads();
+void shared_shape(int* rows, int* cols);
+
 // Streaming kernel (simplex_gm.hip).
 hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s);
 const void* gm_kernel_ptr(int ld);

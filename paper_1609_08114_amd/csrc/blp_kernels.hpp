@@ -50,6 +50,7 @@ struct KParams {
     int32_t* bin_head;  // persistent mode: next entry to take (atomic)
     int32_t bin;
     int32_t direct;       // 1: entry = direct_first + blockIdx.x, no queue
+    int64_t chunk;        // shared-constraint mode: LPs taken per queue pop
     int64_t direct_first;
     // streaming kernel workspace: one slot of ws_slot doubles per workgroup
     double* ws;
@@ -60,6 +61,9 @@ struct KParams {
     unsigned long long* timers;
     // entering rule: 0 largest coefficient, 1 random positive coefficient
     int32_t pivot_rule;
+    // streaming workspace: 0 column-major (element (i, j) at ws[j*ws_ld + i]),
+    // 1 row-major (at ws[i*ws_cols + j])
+    int32_t layout;
     uint64_t seed;
 };
 
@@ -125,9 +129,7 @@ __device__ __forceinline__ int64_t work_item(const KParams& P, int64_t q) {
 // carrying a payload.  Ids are unique within a reduction, so every lane ends
 // with the same winner whatever the combination order.  The id (< 2^15) and
 // the payload position (< 2^16) travel packed in one dword, id in the high
-// half, so comparing packed values orders by id.  Within each 16-lane row
-// the exchange uses DPP (quad permutes, then row rotations by 4 and 8);
-// across rows, gfx950's permlane16/permlane32 swaps (lane ^ 16, lane ^ 32).
+// half, so comparing packed values orders by id.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool key_before(double ak, int aid, double bk, int bid) {
     return ak > bk || (ak == bk && aid < bid);
@@ -138,55 +140,44 @@ __device__ __forceinline__ int pack_id(int id, int pos) { return id == ID_NONE ?
 __device__ __forceinline__ int unpack_id(int p) { return p == PACK_NONE ? ID_NONE : (p >> 16); }
 __device__ __forceinline__ int unpack_pos(int p) { return p == PACK_NONE ? -1 : (p & 0xffff); }
 
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+// Value of the DPP source lane, lanes outside row mask RM keeping their own.
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, RM, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
-
-// Value of lane ^ 16 / lane ^ 32 (lane layout of the swaps checked on the
-// device: the first result holds the lower source half in the upper lanes).
-__device__ __forceinline__ int xor16_i32(int v) {
-    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (threadIdx.x & 16) ? r[0] : r[1];
-}
-__device__ __forceinline__ int xor32_i32(int v) {
-    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (threadIdx.x & 32) ? r[0] : r[1];
-}
-
-template <int CTRL>
-__device__ __forceinline__ void argmax_step_dpp(double& k, int& pk) {
-    const int lo = dpp_i32<CTRL>(__double2loint(k));
-    const int hi = dpp_i32<CTRL>(__double2hiint(k));
-    const double ok = __hiloint2double(hi, lo);
-    const int opk = dpp_i32<CTRL>(pk);
-    if (ok > k || (ok == k && opk < pk)) {
-        k = ok;
-        pk = opk;
-    }
-}
-template <int X>
-__device__ __forceinline__ void argmax_step_swap(double& k, int& pk) {
-    const int lo = X == 16 ? xor16_i32(__double2loint(k)) : xor32_i32(__double2loint(k));
-    const int hi = X == 16 ? xor16_i32(__double2hiint(k)) : xor32_i32(__double2hiint(k));
-    const double ok = __hiloint2double(hi, lo);
-    const int opk = X == 16 ? xor16_i32(pk) : xor32_i32(pk);
-    if (ok > k || (ok == k && opk < pk)) {
-        k = ok;
-        pk = opk;
-    }
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dpp_min_i32(int v) {
+    const int o = __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xF, false);
+    return o < v ? o : v;
 }
 
 // All 64 lanes must be active.  On return id/pos are wave-uniform.
+// Two passes of six DPP steps each: the maximum key (quad permutes, half-row
+// and row mirrors, then row broadcasts 15 and 31 into lane 63), then the
+// minimum packed (id, pos) among the lanes holding that key.  Lanes without
+// a candidate carry key -inf and id ID_NONE; a NaN key is never chosen.
+// Same winner as the pairwise order key_before().
 __device__ __forceinline__ void wave_argmax(double& k, int& id, int& pos) {
-    int pk = pack_id(id, pos);
-    argmax_step_dpp<0xB1>(k, pk);   // quad_perm [1,0,3,2]: lane ^ 1
-    argmax_step_dpp<0x4E>(k, pk);   // quad_perm [2,3,0,1]: lane ^ 2
-    argmax_step_dpp<0x124>(k, pk);  // row_ror:4
-    argmax_step_dpp<0x128>(k, pk);  // row_ror:8
-    argmax_step_swap<16>(k, pk);
-    argmax_step_swap<32>(k, pk);
-    pk = __builtin_amdgcn_readfirstlane(pk);
+    double mx = k;
+    mx = fmax(mx, dpp_f64<0xB1>(mx));        // quad_perm [1,0,3,2]
+    mx = fmax(mx, dpp_f64<0x4E>(mx));        // quad_perm [2,3,0,1]
+    mx = fmax(mx, dpp_f64<0x141>(mx));       // row_half_mirror
+    mx = fmax(mx, dpp_f64<0x140>(mx));       // row_mirror
+    mx = fmax(mx, dpp_f64<0x142, 0xA>(mx));  // row_bcast:15 into rows 1, 3
+    mx = fmax(mx, dpp_f64<0x143, 0xC>(mx));  // row_bcast:31 into rows 2, 3
+    const double top = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mx), 63),
+                                        __builtin_amdgcn_readlane(__double2loint(mx), 63));
+    int pk = k == top ? pack_id(id, pos) : PACK_NONE;
+    pk = dpp_min_i32<0xB1>(pk);
+    pk = dpp_min_i32<0x4E>(pk);
+    pk = dpp_min_i32<0x141>(pk);
+    pk = dpp_min_i32<0x140>(pk);
+    pk = dpp_min_i32<0x142, 0xA>(pk);
+    pk = dpp_min_i32<0x143, 0xC>(pk);
+    pk = __builtin_amdgcn_readlane(pk, 63);
+    k = top;
     id = unpack_id(pk);
     pos = unpack_pos(pk);
 }

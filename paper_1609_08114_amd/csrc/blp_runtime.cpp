@@ -96,6 +96,7 @@ struct blp_handle_s {
     std::vector<uint64_t> graph_sig;
     hipStream_t cap_stream = nullptr;
     DevBuf tune;  // autotuner scratch (sample list + counters)
+    DevBuf shared_ctr;  // queue head of blp_solve_shared
     // host-resident pipeline: two child handles (own buffers), two streams,
     // two device input/output sets
     blp_handle_s* child[2] = {nullptr, nullptr};
@@ -178,6 +179,7 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
     if (opt) o = *opt;
     if (o.mode < 0 || o.mode > 2 || o.variant < -2 || o.workers_per_cu < 0) return BLP_ERR_ARG;
     if (o.pivot_rule != BLP_RULE_LPC && o.pivot_rule != BLP_RULE_RPC) return BLP_ERR_ARG;
+    if (o.layout != BLP_LAYOUT_COLUMN && o.layout != BLP_LAYOUT_ROW) return BLP_ERR_ARG;
     if (!(o.eps_price >= 0) || !(o.eps_piv >= 0) || !(o.eps_feas >= 0)) return BLP_ERR_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return BLP_ERR_HIP;
@@ -406,6 +408,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.eps_piv = h->opt.eps_piv;
     P.eps_feas = h->opt.eps_feas;
     P.pivot_rule = h->opt.pivot_rule;
+    P.layout = h->opt.layout;
     P.seed = h->opt.seed;
 #ifdef BLP_PHASE_TIMERS
     P.timers = h->timers;
@@ -594,6 +597,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
                                (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers};
     for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
     g.push_back((uint64_t)P.pivot_rule);
+    g.push_back((uint64_t)P.layout);
     g.push_back(P.seed);
     if (!sp.uni) {
         // metadata content (the device copy is refreshed on every call, but
@@ -680,6 +684,76 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
 }
 
 // ------------------------------------------------ host-resident pipeline
+blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
+                           const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,
+                           void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (count < 0 || count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    if (m < 1 || n < 1) return fail(h, BLP_ERR_ARG, "m and n must be >= 1");
+    if (!A || !b || !sense) return fail(h, BLP_ERR_ARG, "A, b and sense are required");
+    if (count > 0 && (!C || !out || !out->status || !out->iters || !out->obj || !out->x || !out->y))
+        return fail(h, BLP_ERR_ARG, "C and all five output buffers are required");
+    int rows = 0, cols = 0;
+    shared_shape(&rows, &cols);
+    if (m + 2 > rows || n + 1 > cols)
+        return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need m + 2 <= %d and n + n_art + 1 <= %d", rows, cols);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    // the tableau width depends on how many rows need an artificial variable
+    std::vector<double> hb(m);
+    std::vector<int8_t> hs(m);
+    HIP_TRY(h, hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(hs.data(), sense, (size_t)m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    int nart = 0;
+    for (int i = 0; i < m; ++i) nart += (hs[i] ? -hb[i] : hb[i]) < 0.0;
+    if (n + nart + 1 > cols)
+        return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need n + n_art + 1 <= %d (n_art = %d)", cols, nart);
+    if (count == 0) return BLP_SUCCESS;
+    KParams P{};
+    P.count = count;
+    P.uniform = 1;
+    P.um = m;
+    P.un = n;
+    P.ukind = 0;
+    P.A = A;
+    P.b = b;
+    P.sense = sense;
+    P.c = C;
+    P.status = out->status;
+    P.iters = out->iters;
+    P.obj = out->obj;
+    P.x = out->x;
+    P.y = out->y;
+    P.max_iter = h->opt.max_iter;
+    P.bland_after = h->opt.bland_after;
+    P.eps_price = h->opt.eps_price;
+    P.eps_piv = h->opt.eps_piv;
+    P.eps_feas = h->opt.eps_feas;
+    P.pivot_rule = h->opt.pivot_rule;
+    P.layout = h->opt.layout;
+    P.seed = h->opt.seed;
+#ifdef BLP_PHASE_TIMERS
+    P.timers = h->timers;
+#endif
+    HIP_TRY(h, h->shared_ctr.reserve(sizeof(int32_t) * 64));
+    P.bin_head = h->shared_ctr.as<int32_t>();
+    P.bin = 0;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, shared_kernel_ptr(), shared_threads(), 0) != hipSuccess ||
+        occ < 1)
+        occ = 1;
+    const int64_t workers = (int64_t)occ * h->cu_count;
+    // chunks of consecutive objectives (the warm starts run along a chunk):
+    // at least 8 per chunk, about four chunks per workgroup for balance
+    P.chunk = std::max<int64_t>(8, (count + 4 * workers - 1) / (4 * workers));
+    const int grid = (int)std::min<int64_t>(workers, (count + P.chunk - 1) / P.chunk);
+    HIP_TRY(h, launch_reset(P.bin_head, 1, s));
+    HIP_TRY(h, launch_shared(P, grid, s));
+    return BLP_SUCCESS;
+}
+
 blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outputs* out, int32_t chunks) {
     if (!h) return BLP_ERR_ARG;
     h->err.clear();

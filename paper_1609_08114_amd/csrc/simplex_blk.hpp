@@ -38,14 +38,12 @@ __device__ __forceinline__ void price_regs(int nslots, int lane, int id_lim, dou
     for (int q = 0; q < CS; ++q) {
         const int j = q * 64 + lane;
         const int v = cv[q];
-        if (j < nslots && v < id_lim && d[q] > eps_price) {
-            const double key = bland ? 0.0 : d[q];
-            if (key_before(key, v, bk, bid)) {
-                bk = key;
-                bid = v;
-                bpos = j;
-            }
-        }
+        const double key = bland ? 0.0 : d[q];
+        const bool take = (j < nslots) & (v < id_lim) & (d[q] > eps_price) &
+                          ((key > bk) | ((key == bk) & (v < bid)));
+        bk = take ? key : bk;
+        bid = take ? v : bid;
+        bpos = take ? j : bpos;
     }
     wave_argmax(bk, bid, bpos);
     e_id = bid;
@@ -105,20 +103,42 @@ __device__ __forceinline__ int ratio_regs(int m, int lane, double eps_piv, const
     for (int q = 0; q < RS; ++q) {
         const int i = q * 64 + lane;
         const double a = f[q];
-        if (i < m && !((dead >> q) & 1u) && a > eps_piv) {
-            const double bi = b[q];
-            const double ratio = bi <= 0.0 ? 0.0 : bi / a;
-            if (key_before(-ratio, bs[q], bk, bid)) {
-                bk = -ratio;
-                bid = bs[q];
-                bpos = i;
-            }
-        }
+        const bool cand = (i < m) & !((dead >> q) & 1u) & (a > eps_piv);
+        const double bi = b[q];
+        // the division only where it is a candidate (no spurious inf/nan work)
+        const double ratio = bi <= 0.0 ? 0.0 : bi / (cand ? a : 1.0);
+        const double key = -ratio;
+        const bool take = cand & ((key > bk) | ((key == bk) & (bs[q] < bid)));
+        bk = take ? key : bk;
+        bid = take ? bs[q] : bid;
+        bpos = take ? i : bpos;
     }
     wave_argmax(bk, bid, bpos);
     rmin = -bk;
     leave_id = bid;
     return bid == ID_NONE ? -1 : bpos;
+}
+
+// x / b rounded to nearest, given y = x / b's reciprocal 1.0 / b (an IEEE
+// division) and b_ok = |b| in [2^-500, 2^500]: q = x y is within one ulp of
+// x / b, the residual x - b q is exact in one FMA, and q + residual * y
+// rounded once is the correctly rounded quotient (Markstein's theorem, IBM J.
+// Res. Dev. 34(1), 1990).  Outside the range where no step can overflow or
+// underflow, and for x = 0 (sign of zero), the plain division or the product
+// is used instead, so the result always equals x / b.
+__device__ __forceinline__ double div_rn(double x, double b, double y, bool b_ok) {
+    const double q = x * y;
+    const double ax = fabs(x);
+    const bool zero = x == 0.0;
+    const bool fast = zero | (b_ok & (ax >= 0x1p-500) & (ax <= 0x1p500));
+    double p = zero ? q : __builtin_fma(__builtin_fma(-b, q, x), y, q);
+    if (!fast) {
+        // never taken on ordinary data; the empty volatile asm keeps the
+        // compiler from evaluating the division on every call
+        __asm__ volatile("");
+        p = x / b;
+    }
+    return p;
 }
 
 // Wave-uniform value of a mirror entry (row or slot `idx`).
@@ -143,7 +163,14 @@ __device__ __forceinline__ int mirror_at(const int (&v)[S], int idx) {
     return r;
 }
 
-template <int NW, int GC, int RB, int CB, int WPE>
+// SH: shared-constraint mode.  Every LP k of the launch has the same A, b and
+// row senses (read at offset 0) and its own objective c_k (at k*n; x at k*n,
+// y at k*m).  A workgroup takes chunks of P.chunk consecutive LPs; after the
+// first LP it keeps the tableau and starts the next LP from the current basis,
+// which is primal feasible for every objective: only the objective row is
+// rebuilt (d_j = c_{var j} - sum_i c_{basis i} T[i][j], -z in the rhs cell)
+// and phase 2 resumes, so phase 1 runs once per workgroup.
+template <int NW, int GC, int RB, int CB, int WPE, bool SH = false>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 simplex_blk_kernel(KParams P) {
     constexpr int NT = NW * 64;
@@ -159,6 +186,10 @@ simplex_blk_kernel(KParams P) {
     __shared__ int s_colvar[CP], s_basis[RP], s_artrow[RP], s_rank[RP];
     __shared__ unsigned char s_flag[RP];
     __shared__ int s_k, s_nart, s_bad;
+    // shared-constraint mode: objective coefficients of the basis, per row
+    // group partial sums of the rebuilt objective row, the chunk being served
+    __shared__ double s_cb[SH ? RP : 1], s_part[SH ? GR * CP : 1];
+    __shared__ int64_t s_cur, s_end;
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -172,46 +203,62 @@ simplex_blk_kernel(KParams P) {
     BLP_TDECL;
     const int64_t len = work_len(P);
     bool first = true;
-    for (;;) {
+    unsigned dead = 0;  // bit q: row q*64 + lane is redundant
+    if (SH && t == 0) s_cur = s_end = 0;
+    // next LP index of this workgroup (-1: none); SH takes chunks
+    auto pop = [&]() __attribute__((always_inline)) -> int {
         if (t == 0) {
             int64_t q;
-            if (P.direct)
+            if (SH) {
+                if (s_cur >= s_end) {
+                    const int64_t c0 = (int64_t)atomicAdd(P.bin_head + P.bin, 1) * P.chunk;
+                    s_cur = c0 < len ? c0 : len;
+                    s_end = c0 + P.chunk < len ? c0 + P.chunk : len;
+                }
+                q = s_cur < s_end ? s_cur++ : len;
+            } else if (P.direct) {
                 q = first ? P.direct_first + (int64_t)blockIdx.x : len;
-            else
+            } else {
                 q = atomicAdd(P.bin_head + P.bin, 1);
+            }
             s_k = q < len ? (int)work_item(P, q) : -1;
             s_bad = 0;
         }
         first = false;
         __syncthreads();
-        const int k = s_k;
+        return s_k;
+    };
+    for (;;) {
+        int k = pop();
         if (k < 0) break;
         BLP_T(t_load0);
 
         // ------------------------------------------------------------ load
-        const LpRef L = lp_ref(P, k);
+        LpRef L = lp_ref(P, k);
+        LpRef Lin = L;  // where the constraint data are read
+        if (SH) Lin.a_off = Lin.row_off = 0;
         const int m = L.m, n = L.n;
         if (m > RP - 2 || n + 1 > CP) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
             __syncthreads();
             continue;
         }
-        int bad = prep_rows<NT>(P, L, t, s_sig, s_b, s_flag);
+        int bad = prep_rows<NT>(P, Lin, t, s_sig, s_b, s_flag);
         for (int j = t; j < n; j += NT) s_c[j] = P.c[L.col_off + j];
         // A straight into the tile (scaled below, once the row signs are known)
+        // with range-checked buffer loads: the resource covers this LP's m x n
+        // block, so rows >= m read as 0; columns >= n get an offset beyond it.
         {
-            const double* A = P.A + L.a_off;
-            const bool any = m > 0 && n > 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<double*>(P.A + Lin.a_off), (short)0, m * n * (int)sizeof(double), 0x00020000);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int i = i0 + r;
+            for (int c = 0; c < CB; ++c) {
+                const int j = c * GC + tcb;
+                const unsigned cofs = j < n ? (unsigned)(i0 * n + j) * 8u : 0x80000000u;
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const int j = c * GC + tcb;
-                    const bool in = i < m && j < n;
-                    const double a = any ? A[in ? (int64_t)i * n + j : 0] : 0.0;
-                    T[r][c] = in ? a : 0.0;
-                }
+                for (int r = 0; r < RB; ++r)
+                    T[r][c] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(cofs + (unsigned)(r * n) * 8u), 0, 0));
             }
         }
         __syncthreads();
@@ -231,7 +278,7 @@ simplex_blk_kernel(KParams P) {
                 if (j < n) {
                     for (int q = 0; q < nart; ++q) {
                         const int ii = s_artrow[q];
-                        acc = acc + s_sig[ii] * P.A[L.a_off + (int64_t)ii * n + j];
+                        acc = acc + s_sig[ii] * P.A[Lin.a_off + (int64_t)ii * n + j];
                     }
                 } else if (j < n + nart) {
                     acc = -1.0;
@@ -242,30 +289,34 @@ simplex_blk_kernel(KParams P) {
             }
             __syncthreads();
         }
-        // finish the tile: signs, surplus columns, rhs, objective rows
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int i = i0 + r;
-            const double sg = s_sig[i < m ? i : 0];
+        // finish the tile with selects only (no divergent branch around the
+        // tile): row signs on the A block, +0 beyond it, then the rhs column,
+        // the surplus columns of the artificial rows and the objective rows
+        {
+            const bool obj_grp = trb == GR - 1;  // holds rows ROW_W and ROW_OBJ
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const int j = c * GC + tcb;
-                double v = 0.0;
-                if (i < m) {
-                    if (j < n) {
-                        bad |= !isfinite(T[r][c]);
-                        v = sg * T[r][c];
-                    } else if (j < n + nart) {
-                        v = s_artrow[j - n] == i ? -1.0 : 0.0;
-                    } else if (j == COL_RHS) {
-                        v = s_b[i];
-                    }
-                } else if (i == ROW_OBJ) {
-                    v = j < n ? s_c[j] : 0.0;
-                } else if (i == ROW_W && nart > 0) {
-                    v = s_w[j];
+                const bool inA = j < n;
+                const bool rhs = c == CB - 1 && tcb == GC - 1;
+                const bool art = j >= n && j < n + nart;
+                const int ar = s_artrow[art ? j - n : 0];
+                const double cj = s_c[inA ? j : 0];
+                const double wj = nart > 0 ? s_w[j] : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int i = i0 + r;
+                    const bool row = i < m;
+                    const double sg = s_sig[row ? i : 0];
+                    const double bi = s_b[row ? i : 0];
+                    bad |= !isfinite(T[r][c]);
+                    double v = inA && row ? sg * T[r][c] : 0.0;
+                    v = row && rhs ? bi : v;
+                    v = row && art ? (ar == i ? -1.0 : 0.0) : v;
+                    if (r == RB - 1) v = obj_grp ? (inA ? cj : 0.0) : v;
+                    if (r == RB - 2) v = obj_grp ? wj : v;
+                    T[r][c] = v;
                 }
-                T[r][c] = v;
             }
         }
         // register mirrors (identical in every wave)
@@ -290,20 +341,141 @@ simplex_blk_kernel(KParams P) {
             continue;
         }
         const double w0 = mirror_at(bR, ROW_W);
+        dead = 0;
+        int mode = nart > 0 ? 1 : 2;
         const int max_iter = P.max_iter > 0 ? P.max_iter : 50 * (m + n);
         const int bland_after = P.bland_after > 0 ? P.bland_after : (m > n ? m : n);
         const int id_lim = n + m;
         int iters = 0, degen = 0, st = -1;
-        unsigned dead = 0;  // bit q: row q*64 + lane is redundant
 
+        // outputs of LP k from the mirrors
+        auto extract = [&]() __attribute__((always_inline)) {
+            BLP_T(t_x0);
+            __syncthreads();
+            if (t < 64) {
+#pragma unroll
+                for (int q = 0; q < CS; ++q) {
+                    const int j = q * 64 + lane;
+                    if (j < CP) {
+                        s_p[1][j] = dO[q];
+                        s_colvar[j] = cv[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < RS; ++q) {
+                    const int i = q * 64 + lane;
+                    if (i < RP) s_f[1][i] = bR[q];
+                    if (i < m) {
+                        s_basis[i] = bs[q];
+                        if ((dead >> q) & 1u) s_flag[i] |= RF_DEAD;
+                    }
+                }
+            }
+            __syncthreads();
+            write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, COL_RHS, s_p[1], s_f[1], s_colvar, s_basis, s_flag, s_p[0],
+                              s_f[0]);
+            __syncthreads();
+            BLP_T(t_x1);
+            BLP_TACC(TM_EXTRACT, t_x0, t_x1);
+            BLP_TCOUNT(TM_PIVOTS, (unsigned long long)iters);
+            BLP_TCOUNT(TM_LPS, 1ull);
+        };
         // ------------------------------------------------------ pivot loop
         // mode 1 = phase 1, 2 = phase 2, 3 = driving the remaining basic
-        // artificials out after a feasible phase 1.
-        int mode = nart > 0 ? 1 : 2, drive_r = 0, buf = 0;
+        // artificials out after a feasible phase 1.  Step 1 for the next
+        // pivot runs on the updated mirrors before the tile's rank-1 update,
+        // so the two overlap.
+        int drive_r = 0, buf = 0;
+        int e_id = ID_NONE, e = -1;  // entering variable and slot from Step 1
+        auto step1 = [&]() __attribute__((always_inline)) {
+            double da[CS];  // the active objective row
+#pragma unroll
+            for (int q = 0; q < CS; ++q) da[q] = mode == 1 ? dW[q] : dO[q];
+            if (P.pivot_rule == 1 && degen < bland_after)
+                price_rpc_regs(COL_RHS, lane, id_lim, P.eps_price, P.seed, k, iters, da, cv, e_id, e);
+            else
+                price_regs(COL_RHS, lane, id_lim, P.eps_price, degen >= bland_after, da, cv, e_id, e);
+        };
+        step1();
         BLP_T(t_load1);
         BLP_TACC(TM_LOAD, t_load0, t_load1);
         for (;;) {
-            int e_id, e, l = -1, lv = ID_NONE;
+            if (SH && st != -1) {
+                // SH: LP k is done (st >= 0) or its objective was not finite
+                // (st == -2, outputs written).  Extract it, take the next
+                // objective and rebuild the objective row on the current
+                // basis; phase 2 resumes from there.  If phase 1 ended the
+                // solve (infeasible), every objective gets that outcome.
+                if (st >= 0) extract();
+                const bool same = st >= 0 && mode != 2;
+                k = pop();
+                if (k < 0) break;
+                L = lp_ref(P, k);
+                if (same) continue;
+                int badc = 0;
+                for (int j = t; j < n; j += NT) {
+                    const double cj = P.c[L.col_off + j];
+                    badc |= !isfinite(cj);
+                    s_c[j] = cj;
+                }
+                if (badc) atomicOr(&s_bad, 1);
+                __syncthreads();
+                if (s_bad) {
+                    write_numerical<NT>(P, L, k, t, ST_NUMERICAL);
+                    __syncthreads();
+                    st = -2;  // written; take the next objective
+                    continue;
+                }
+                if (t < 64) {
+#pragma unroll
+                    for (int q = 0; q < RS; ++q) {
+                        const int i = q * 64 + lane;
+                        if (i < RP) s_cb[i] = (i < m && bs[q] < n) ? s_c[bs[q]] : 0.0;
+                    }
+                }
+                __syncthreads();
+                // partial sums over this thread's rows, in row order
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) acc = __builtin_fma(s_cb[i0 + r], T[r][c], acc);
+                    s_part[trb * CP + c * GC + tcb] = acc;
+                }
+                __syncthreads();
+                if (t < 64) {
+#pragma unroll
+                    for (int q = 0; q < CS; ++q) {
+                        const int j = q * 64 + lane;
+                        if (j < CP) {
+                            double z = 0.0;
+                            for (int g = 0; g < GR; ++g) z = z + s_part[g * CP + j];
+                            const int v = cv[q];
+                            s_p[0][j] = (v < n ? s_c[v] : 0.0) - z;
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < CS; ++q) {
+                    const int j = q * 64 + lane;
+                    dO[q] = j < CP ? s_p[0][j] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < RS; ++q)
+                    if (q * 64 + lane == ROW_OBJ) bR[q] = s_p[0][COL_RHS];
+                if (trb == GR - 1) {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) T[RB - 1][c] = s_p[0][c * GC + tcb];
+                }
+                __syncthreads();
+                st = -1;
+                iters = 0;
+                degen = 0;
+                step1();
+                continue;
+            }
+            int l = -1, lv = ID_NONE;
             double rmin = 1.0;
             BLP_T(t_p0);
             if (mode == 3) {
@@ -318,6 +490,7 @@ simplex_blk_kernel(KParams P) {
                 if (r0 < 0) {
                     mode = 2;
                     degen = 0;
+                    step1();
                     continue;
                 }
                 drive_r = r0 + 1;
@@ -359,20 +532,15 @@ simplex_blk_kernel(KParams P) {
                 e_id = bid;
                 lv = mirror_at(bs, r0);
             } else {
-                double da[CS];  // the active objective row
-#pragma unroll
-                for (int q = 0; q < CS; ++q) da[q] = mode == 1 ? dW[q] : dO[q];
-                if (P.pivot_rule == 1 && degen < bland_after)
-                    price_rpc_regs(COL_RHS, lane, id_lim, P.eps_price, P.seed, k, iters, da, cv, e_id, e);
-                else
-                    price_regs(COL_RHS, lane, id_lim, P.eps_price, degen >= bland_after, da, cv, e_id, e);
                 if (e_id == ID_NONE) {
                     if (mode == 2) {
                         st = ST_OPTIMAL;
+                        if (SH) continue;
                         break;
                     }
                     if (mirror_at(bR, ROW_W) > P.eps_feas * (1.0 + w0)) {
                         st = ST_INFEASIBLE;
+                        if (SH) continue;
                         break;
                     }
                     mode = 3;
@@ -381,6 +549,7 @@ simplex_blk_kernel(KParams P) {
                 }
                 if (iters >= max_iter) {
                     st = ST_ITER_LIMIT;
+                    if (SH) continue;
                     break;
                 }
             }
@@ -413,108 +582,80 @@ simplex_blk_kernel(KParams P) {
                 l = ratio_regs(m, lane, P.eps_piv, fr, bR, bs, dead, rmin, lv);
                 if (l < 0) {
                     st = mode == 2 ? ST_UNBOUNDED : ST_NUMERICAL;
+                    if (SH) continue;
                     break;
                 }
             }
-            const double pe = s_f[buf][l];
+            const double pe = mirror_at(fr, l);
             // Step 3's new pivot row, divided by the owners of row l
             if (trb == l / RB) {
                 const int rl = __builtin_amdgcn_readfirstlane(l % RB);
+                const double y = 1.0 / pe;
+                const double ape = fabs(pe);
+                const bool pe_ok = ape >= 0x1p-500 && ape <= 0x1p500;
+                const int de = e - tcb;  // slot c*GC + tcb is e iff c*GC == de
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
                     if (r == rl) {
 #pragma unroll
                         for (int c = 0; c < CB; ++c) {
-                            const int j = c * GC + tcb;
-                            const double p = (j == e ? 1.0 : T[r][c]) / pe;
-                            s_p[buf][j] = p;
+                            const double p = div_rn(c * GC == de ? 1.0 : T[r][c], pe, y, pe_ok);
+                            s_p[buf][c * GC + tcb] = p;
                             T[r][c] = p;
                         }
                     }
             }
             __syncthreads();
             BLP_T(t_p3);
-            // rank-1 update; the pivot row keeps p (fma(+0, p, p) = p)
-            {
-                double nf[RB], pc[CB];
+            double nf[RB], pc[CB];
+            const int dl = l - i0;  // row i0 + r is l iff r == dl
 #pragma unroll
-                for (int r = 0; r < RB; ++r) nf[r] = i0 + r == l ? 0.0 : -s_f[buf][i0 + r];
+            for (int r = 0; r < RB; ++r) nf[r] = r == dl ? 0.0 : -s_f[buf][i0 + r];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) pc[c] = s_p[buf][c * GC + tcb];
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int c = 0; c < CB; ++c) T[r][c] = __builtin_fma(nf[r], pc[c], T[r][c]);
-            }
-            // the same update on the mirrors
+            for (int c = 0; c < CB; ++c) pc[c] = s_p[buf][c * GC + tcb];
+            // Step 3 on the mirrors
             {
                 const double pr = s_p[buf][COL_RHS];
                 const double fO = s_f[buf][ROW_OBJ], fW = s_f[buf][ROW_W];
+                const int el = e - lane, ll = l - lane;  // slot / row q*64 + lane is e / l iff q*64 == el / ll
 #pragma unroll
                 for (int q = 0; q < CS; ++q) {
                     const int j = q * 64 + lane;
                     if (j < CP) {
                         const double pj = s_p[buf][j];
-                        if (j == e) {
-                            dO[q] = 0.0;
-                            dW[q] = 0.0;
-                            cv[q] = lv;
-                        }
-                        dO[q] = __builtin_fma(-fO, pj, dO[q]);
-                        dW[q] = __builtin_fma(-fW, pj, dW[q]);
+                        const bool ent = q * 64 == el;
+                        dO[q] = __builtin_fma(-fO, pj, ent ? 0.0 : dO[q]);
+                        dW[q] = __builtin_fma(-fW, pj, ent ? 0.0 : dW[q]);
+                        cv[q] = ent ? lv : cv[q];
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < RS; ++q) {
-                    const int i = q * 64 + lane;
-                    if (i == l) {
-                        bR[q] = pr;
-                        bs[q] = e_id;
-                    } else {
-                        bR[q] = __builtin_fma(-fr[q], pr, bR[q]);
-                    }
+                    const bool piv = q * 64 == ll;
+                    bR[q] = piv ? pr : __builtin_fma(-fr[q], pr, bR[q]);
+                    bs[q] = piv ? e_id : bs[q];
                 }
             }
+            ++iters;
+            if (mode != 3) {
+                degen = rmin == 0.0 ? degen + 1 : 0;
+                step1();  // next pivot's entering column, overlapping the update below
+            }
+            // Step 3 on the tile; the pivot row keeps p (fma(+0, p, p) = p)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) T[r][c] = __builtin_fma(nf[r], pc[c], T[r][c]);
             BLP_T(t_p4);
             BLP_TACC(TM_PRICE, t_p0, t_p1);
             BLP_TACC(TM_PUBCOL, t_p1, t_p2);
             BLP_TACC(TM_RATIO, t_p2, t_p3);
             BLP_TACC(TM_PIVOT, t_p3, t_p4);
-            ++iters;
-            if (mode != 3) degen = rmin == 0.0 ? degen + 1 : 0;
             buf ^= 1;
         }
 
         // ------------------------------------------------------ extraction
-        BLP_T(t_x0);
-        __syncthreads();
-        if (t < 64) {
-#pragma unroll
-            for (int q = 0; q < CS; ++q) {
-                const int j = q * 64 + lane;
-                if (j < CP) {
-                    s_p[1][j] = dO[q];
-                    s_colvar[j] = cv[q];
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RS; ++q) {
-                const int i = q * 64 + lane;
-                if (i < RP) s_f[1][i] = bR[q];
-                if (i < m) {
-                    s_basis[i] = bs[q];
-                    if ((dead >> q) & 1u) s_flag[i] |= RF_DEAD;
-                }
-            }
-        }
-        __syncthreads();
-        write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, COL_RHS, s_p[1], s_f[1], s_colvar, s_basis, s_flag, s_p[0],
-                          s_f[0]);
-        __syncthreads();
-        BLP_T(t_x1);
-        BLP_TACC(TM_EXTRACT, t_x0, t_x1);
-        BLP_TCOUNT(TM_PIVOTS, (unsigned long long)iters);
-        BLP_TCOUNT(TM_LPS, 1ull);
+        if (!SH) extract();
     }
     BLP_TFLUSH();
 }

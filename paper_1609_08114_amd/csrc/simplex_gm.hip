@@ -30,8 +30,12 @@ __host__ __device__ inline size_t gm_lds_bytes(int ld, int cols) {
     return (size_t)cols * (8 + 8 + 4) + (size_t)ld * (8 + 8 + 8 + 4 + 4 + 4 + 1) + 64;
 }
 
-// QM: 64-row chunks per column held by one lane (ld <= 64 QM).
-template <int NW, int QM>
+// QM: 64-row chunks per column held by one lane (ld <= 64 QM).  RM: the
+// workspace is row-major instead (element (i, j) at ws[i*ws_cols + j]) with
+// the same thread mapping, so the column reads and the update are strided
+// across lanes: the non-coalesced variant of Sec. 4.3's comparison, kept for
+// the layout measurement; results are identical.
+template <int NW, int QM, bool RM>
 __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     constexpr int NT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -52,6 +56,8 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double* const Tg = P.ws + (int64_t)blockIdx.x * P.ws_slot;
     const int ROW_OBJ = ld - 1, ROW_W = ld - 2;
+    // workspace index of tableau cell (i, j)
+    auto at = [&](int i, int j) -> int64_t { return RM ? (int64_t)i * cg_max + j : (int64_t)j * ld + i; };
 
     const int64_t len = work_len(P);
     bool first = true;
@@ -100,7 +106,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             for (int j = lane; j < n; j += 64) {
                 const double a = P.A[L.a_off + (int64_t)i * n + j];
                 bad |= !isfinite(a);
-                Tg[(int64_t)j * ld + i] = sg * a;
+                Tg[at(i, j)] = sg * a;
             }
         }
         // the other cells, column by column
@@ -127,7 +133,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                     }
                     v = acc;
                 }
-                Tg[(int64_t)j * ld + i] = v;
+                Tg[at(i, j)] = v;
             }
         }
         if (bad) atomicOr(&s_bad, 1);
@@ -141,10 +147,10 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
         }
         int phase = nart > 0 ? 1 : 2;
         auto mirror_row = [&](int row) {
-            for (int j = t; j < C; j += NT) S.d[j] = Tg[(int64_t)j * ld + row];
+            for (int j = t; j < C; j += NT) S.d[j] = Tg[at(row, j)];
         };
         mirror_row(phase == 1 ? ROW_W : ROW_OBJ);
-        for (int i = t; i < ld; i += NT) S.b[i] = Tg[(int64_t)RHS * ld + i];
+        for (int i = t; i < ld; i += NT) S.b[i] = Tg[at(i, RHS)];
         __syncthreads();
         const double w0 = S.b[ROW_W];
         const int max_iter = P.max_iter > 0 ? P.max_iter : 50 * (m + n);
@@ -172,7 +178,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                     continue;
                 }
                 ++drive_r;
-                for (int j = t; j < C; j += NT) S.p[j] = Tg[(int64_t)j * ld + r0];
+                for (int j = t; j < C; j += NT) S.p[j] = Tg[at(r0, j)];
                 __syncthreads();
                 double bk = -__builtin_inf();
                 int bid = ID_NONE, bpos = -1;
@@ -218,8 +224,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 }
             }
             // entering column -> LDS
-            const double* colE = Tg + (int64_t)e * ld;
-            for (int i = t; i < ld; i += NT) S.f[i] = colE[i];
+            for (int i = t; i < ld; i += NT) S.f[i] = Tg[at(i, e)];
             __syncthreads();
             if (mode != 3) {
                 l = ratio_test(m, lane, P.eps_piv, S.f, S.b, S.basis, S.flag, rmin);
@@ -231,7 +236,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             // Step 3: NewPivotRow = OldPivotRow / PE (the entering slot takes
             // the leaving variable's column, whose pivot-row entry is 1 / PE)
             const double pe = S.f[l];
-            for (int j = t; j < C; j += NT) S.p[j] = (j == e ? 1.0 : Tg[(int64_t)j * ld + l]) / pe;
+            for (int j = t; j < C; j += NT) S.p[j] = (j == e ? 1.0 : Tg[at(l, j)]) / pe;
             __syncthreads();
             const int act = phase == 1 ? ROW_W : ROW_OBJ;
             // this lane's rows i = lane + 64 q and their pivot-column entries
@@ -242,14 +247,13 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 nf[q] = i < ld ? -S.f[i] : 0.0;
             }
             for (int j = wave; j < C; j += NW) {
-                double* col = Tg + (int64_t)j * ld;
                 const double pj = S.p[j];
                 const bool je = j == e;
                 double v[QM];
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
                     const int i = lane + 64 * q;
-                    v[q] = (i < ld && !je) ? col[i] : 0.0;
+                    v[q] = (i < ld && !je) ? Tg[at(i, j)] : 0.0;
                 }
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
@@ -257,7 +261,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                     if (i < ld) {
                         double w = __builtin_fma(nf[q], pj, v[q]);
                         w = i == l ? pj : w;
-                        col[i] = w;
+                        Tg[at(i, j)] = w;
                         if (i == act) S.d[j] = w;
                         if (j == RHS) S.b[i] = w;
                     }
@@ -282,7 +286,10 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
 
 template <int QM>
 static hipError_t launch_gm_q(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((simplex_gm_kernel<8, QM>), dim3(grid), dim3(512), lds_bytes, s, P);
+    if (P.layout == 1)
+        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, true>), dim3(grid), dim3(512), lds_bytes, s, P);
+    else
+        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, false>), dim3(grid), dim3(512), lds_bytes, s, P);
     return hipGetLastError();
 }
 static int gm_chunks(int ld) { return ld <= 64 ? 1 : ld <= 128 ? 2 : ld <= 256 ? 4 : ld <= 512 ? 8 : ld <= 1024 ? 16 : 32; }
@@ -298,12 +305,12 @@ hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s
 }
 const void* gm_kernel_ptr(int ld) {
     switch (gm_chunks(ld)) {
-        case 1: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 1>);
-        case 2: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 2>);
-        case 4: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4>);
-        case 8: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 8>);
-        case 16: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 16>);
-        default: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 32>);
+        case 1: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 1, false>);
+        case 2: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 2, false>);
+        case 4: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4, false>);
+        case 8: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 8, false>);
+        case 16: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 16, false>);
+        default: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 32, false>);
     }
 }
 int gm_threads() { return 512; }

@@ -400,6 +400,20 @@ static const void* kernel_ptr_blk() {
     return reinterpret_cast<const void*>(&simplex_blk_kernel<NW, GC, RB, CB, WPE>);
 }
 
+// Shared-constraint mode (one A, b; many objectives): the block kernel with a
+// 112 x 112 tile.
+constexpr int kSharedRows = 112, kSharedCols = 112;
+hipError_t launch_shared(const KParams& P, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((simplex_blk_kernel<4, 16, 7, 7, 2, true>), dim3(grid), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+const void* shared_kernel_ptr() { return reinterpret_cast<const void*>(&simplex_blk_kernel<4, 16, 7, 7, 2, true>); }
+int shared_threads() { return 256; }
+void shared_shape(int* rows, int* cols) {
+    *rows = kSharedRows;
+    *cols = kSharedCols;
+}
+
 #define BLP_BLK_VARIANT(NAME, NW, GC, RB, CB, WPE)                                                    \
     {NAME, (NW) * 64, (NW) * 64 / (GC) * (RB), (GC) * (CB), &launch_blk<NW, GC, RB, CB, WPE>, \
      &kernel_ptr_blk<NW, GC, RB, CB, WPE>},

@@ -170,9 +170,9 @@ def _crafted_lps():
 
 
 def test_every_variant_on_crafted_and_degenerate():
-    """Each register-tile variant, forced, on the crafted statuses, dead rows
-    after phase 1, degenerate and cycling LPs: identical bits to the oracle's
-    strict comparison."""
+    """Each register-tile variant, forced, on the crafted statuses, repeated
+    rows with mixed senses (phase-1 drive-out), degenerate and cycling LPs:
+    identical bits to the oracle's strict comparison."""
     import paper_1609_08114_amd as blp
     hb = crafted_batch(_crafted_lps())
     o = oracle_solve(hb)

@@ -1,0 +1,157 @@
+"""Shared constraints, many objectives (blp_solve_shared, the support-function
+sampling of Sec. 7): every objective's status and optimum against the
+oracle solving that LP on its own.  The warm-started pivot path differs from
+a cold solve, so objectives are compared to 1e-9 relative (not bit for bit)
+and x, y only where the optimum is non-degenerate."""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from solve_util import REL, crafted_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _shared_gpu(A, b, sense, C):
+    import torch
+
+    import paper_1609_08114_amd as blp
+    dev = torch.device("cuda")
+    s = blp.Solver()
+    try:
+        out = s.solve_shared(torch.from_numpy(np.ascontiguousarray(A, np.float64).ravel()).to(dev),
+                             torch.from_numpy(np.ascontiguousarray(b, np.float64)).to(dev),
+                             torch.from_numpy(np.ascontiguousarray(sense, np.int8)).to(dev),
+                             torch.from_numpy(np.ascontiguousarray(C, np.float64)).to(dev))
+        torch.cuda.synchronize()
+        K, n, m = C.shape[0], C.shape[1], len(b)
+        return {"status": out["status"][:K].cpu().numpy(), "iters": out["iters"][:K].cpu().numpy(),
+                "obj": out["obj"][:K].cpu().numpy(), "x": out["x"][:K * n].cpu().numpy().reshape(K, n),
+                "y": out["y"][:K * m].cpu().numpy().reshape(K, m)}
+    finally:
+        s.close()
+
+
+def _oracle(A, b, sense, C):
+    lps = [dict(A=A, b=b, c=c, sense=sense) for c in C]
+    return oracle.solve_batch(crafted_batch(lps))
+
+
+def _check(A, b, sense, C, tag):
+    g = _shared_gpu(A, b, sense, C)
+    o = _oracle(A, b, sense, C)
+    K, n = C.shape
+    m = len(b)
+    bad = np.nonzero(g["status"] != o["status"])[0]
+    assert bad.size == 0, f"{tag}: status differs at {bad[:10]}: {g['status'][bad[:10]]} vs {o['status'][bad[:10]]}"
+    ok = o["status"] == oracle.OPTIMAL
+    rel = np.abs(g["obj"][ok] - o["obj"][ok]) / np.maximum(1.0, np.abs(o["obj"][ok]))
+    assert (rel <= REL).all(), f"{tag}: obj relerr {rel.max():.3e}"
+    inf = np.isin(o["status"], (oracle.INFEASIBLE, oracle.UNBOUNDED))
+    assert np.array_equal(g["obj"][inf], o["obj"][inf]), tag
+    # x and y where the optimum is unique (basic values and reduced costs away from 0)
+    ox = o["x"].reshape(K, n)
+    oy = o["y"].reshape(K, m)
+    checked = 0
+    for k in np.nonzero(ok)[0]:
+        x, y = ox[k], oy[k]
+        slack = np.where(np.asarray(sense) == 0, b - A @ x, A @ x - b)
+        scale = max(1.0, float(np.abs(b).max()))
+        nbasic = (x > 1e-7 * scale).sum() + (slack > 1e-7 * scale).sum()
+        d = C[k] - A.T @ y
+        if nbasic != m or (np.abs(d[x <= 1e-7 * scale]) <= 1e-7).any() or (np.abs(y[slack <= 1e-7 * scale]) <= 1e-7).any():
+            continue
+        assert np.allclose(g["x"][k], x, rtol=1e-9, atol=1e-9 * scale), (tag, k)
+        assert np.allclose(g["y"][k], y, rtol=1e-9, atol=1e-9 * max(1.0, np.abs(y).max())), (tag, k)
+        checked += 1
+    return g, o, checked
+
+
+def test_type1_polytope_many_directions():
+    # one workload-2 polytope (m = n = 100), 600 objectives: 300 from the
+    # workload's own distribution, 300 unit directions (support function)
+    hb = lpgen.config(2, [7])
+    lp = hb.lp(0)
+    A, b, sense = lp["A"], lp["b"], lp["sense"]
+    rng = np.random.default_rng(21)
+    C1 = rng.uniform(1, 10, size=(300, 100))
+    G = rng.normal(size=(300, 100))
+    C2 = G / np.linalg.norm(G, axis=1, keepdims=True)
+    g, o, checked = _check(A, b, sense, np.vstack([C1, C2]), "type1")
+    assert (o["status"] == oracle.OPTIMAL).all() and checked > 100
+
+
+def test_directions_swept_along_a_circle():
+    # support-function sampling: directions cos(t) u + sin(t) v, t stepping
+    # around a circle; neighbouring optima share most of their basis, so the
+    # warm starts need far fewer pivots than cold solves
+    hb = lpgen.config(2, [11])
+    lp = hb.lp(0)
+    A, b, sense = lp["A"], lp["b"], lp["sense"]
+    rng = np.random.default_rng(4)
+    u, v = rng.normal(size=(2, 100))
+    t = np.linspace(0.0, 2.0 * np.pi, 2048, endpoint=False)
+    C = np.cos(t)[:, None] * u + np.sin(t)[:, None] * v
+    g, o, _ = _check(A, b, sense, C, "sweep")
+    assert g["iters"].mean() < 0.5 * o["iters"].mean(), (g["iters"].mean(), o["iters"].mean())
+
+
+def test_type2_polytope_phase1_once():
+    # ">=" rows: the origin is infeasible, phase 1 runs once per workgroup
+    hb = lpgen.config(4, range(0, 400))
+    k = next(i for i in range(hb.count) if hb.kind[i] == 0 and 20 <= hb.m[i] <= 60 and 20 <= hb.n[i] <= 60
+             and (hb.sense[hb.row_off[i]:hb.row_off[i] + hb.m[i]] != 0).any())
+    lp = hb.lp(k)
+    A, b, sense = lp["A"], lp["b"], lp["sense"]
+    n = A.shape[1]
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(400, n))
+    C = G / np.linalg.norm(G, axis=1, keepdims=True)
+    g, o, _ = _check(A, b, sense, C, "type2")
+    assert (o["status"] == oracle.OPTIMAL).all()
+
+
+def test_mixed_outcomes_and_bad_objectives():
+    # an unbounded recession direction for some objectives, NaN in one
+    A = np.array([[1.0, -1.0, 0.0], [-1.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 1.0, 1.0]])
+    b = np.array([2.0, 3.0, 5.0, 1.0])
+    sense = np.array([0, 0, 0, 1], np.int8)  # a strip in (x1, x2), unbounded along (1, 1)
+    rng = np.random.default_rng(9)
+    C = rng.integers(-3, 4, size=(500, 3)).astype(float)
+    C[17, 1] = np.nan
+    g = _shared_gpu(A, b, sense, C)
+    assert g["status"][17] == oracle.NUMERICAL
+    keep = np.ones(len(C), bool)
+    keep[17] = False
+    _check(A, b, sense, C[keep], "mixed")
+    st = _oracle(A, b, sense, C[keep])["status"]
+    assert set(np.unique(st)) >= {oracle.OPTIMAL, oracle.UNBOUNDED}
+
+
+def test_infeasible_constraints():
+    A = np.array([[1.0, 1.0], [1.0, 1.0]])
+    b = np.array([1.0, 3.0])
+    sense = np.array([0, 1], np.int8)
+    C = np.random.default_rng(2).normal(size=(50, 2))
+    g, o, _ = _check(A, b, sense, C, "infeasible")
+    assert (g["status"] == oracle.INFEASIBLE).all()
+
+
+def test_shared_errors():
+    import torch
+
+    import paper_1609_08114_amd as blp
+    s = blp.Solver()
+    dev = torch.device("cuda")
+    A = torch.ones(200 * 5, dtype=torch.float64, device=dev)
+    b = torch.ones(200, dtype=torch.float64, device=dev)
+    sense = torch.zeros(200, dtype=torch.int8, device=dev)
+    C = torch.ones(3, 5, dtype=torch.float64, device=dev)
+    with pytest.raises(blp.BlpError) as ei:
+        s.solve_shared(A, b, sense, C)
+    assert ei.value.code == blp.BLP_ERR_TOO_LARGE
+    out = s.solve_shared(A[:10], b[:2], sense[:2], C[:0])
+    torch.cuda.synchronize()
+    assert out["status"].numel() == 1  # nothing solved, nothing written
+    s.close()
