@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 METRIC = "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr\u22641e-9"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_simplex_reg_100x100.json")
-KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_common.hpp",
-                  "paper_1609_08114_amd/csrc/blp_kernels.hpp", "paper_1609_08114_amd/csrc/variants.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel__type1_m100_n100_K50000.json")
+KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_blk.hpp",
+                  "paper_1609_08114_amd/csrc/simplex_common.hpp", "paper_1609_08114_amd/csrc/blp_kernels.hpp",
+                  "paper_1609_08114_amd/csrc/variants.hpp"]
 
 
 def log(*a):
@@ -84,10 +85,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classes", action="store_true")
     ap.add_argument("--no-host", action="store_true")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic file from the counter_collection.csv of a FETCH_SIZE and a WRITE_SIZE "
+                         "run of --counter-pass, then exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only a 1 GiB device copy followed by one persistent solve of the batch "
                          "(the workload of the HBM-counter runs)")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, batch=args.batch)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch shards across GPUs "
               "with no exchange, so run one process per GPU instead.", file=sys.stderr)
@@ -259,6 +266,35 @@ def rate_host_resident(blp, torch, hb, ref_obj, steps=3):
     out_bytes = sum(t.numel() * t.element_size() for t in outs)
     return {"value": round(K / dt, 1), "unit": "LPs/s", "ms": round(dt * 1e3, 3), "pcie_bytes": in_bytes + out_bytes,
             "obj_identical_to_resident": same}
+
+
+def write_traffic(fetch_csv: str, write_csv: str, batch: int) -> None:
+    """HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
+    runs of --counter-pass, each counter scaled by what it reads for the
+    1 GiB device copy of the same run."""
+    import csv
+
+    def read(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+    f = read(fetch_csv, "FETCH_SIZE")
+    w = read(write_csv, "WRITE_SIZE")
+    copy = next(k for k in f if "copyBuffer" in k or "copy" in k.lower())
+    kib = float(1 << 20)  # the copy moves 1 GiB each way
+    ff, fw = kib / f[copy][0], kib / w[copy][0]
+    simplex = [k for k in f if "simplex_" in k]
+    dom = max(simplex, key=lambda k: f[k][0])
+    fetch_b = f[dom][0] * ff * 1024.0
+    write_b = w[dom][0] * fw * 1024.0
+    out = {"kernel": dom, "batch": batch, "kernel_source_hash": kernel_source_hash(),
+           "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+           "fetch_bytes": fetch_b, "write_bytes": write_b, "bytes_per_launch": fetch_b + write_b}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out))
 
 
 def counter_pass(blp, torch, lpgen, K):

@@ -189,13 +189,18 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_o
  * device pointers; out->status/iters/obj have count entries, out->x count x n
  * (x of LP k at k*n), out->y count x m (at k*m); all device, caller-owned
  * (C and out may be NULL when count is 0).
- * Each workgroup runs phase 1 once and starts every further objective from
- * the previous optimal basis (only the objective row is rebuilt), so iteration
- * counts and, at degenerate optima, x and y may differ from independent
- * solves; statuses and optima do not.  Needs m + 2 <= 112 and
+ * When consecutive objectives point in close directions (cosine > 0.9 for at
+ * least half of the first 64 pairs), each workgroup runs phase 1 once and
+ * starts every further objective whose direction is that close to the
+ * previous one from the previous optimal basis (only the objective row is
+ * rebuilt); other objectives, or every objective when the directions are
+ * unrelated, are solved from scratch.  Iteration counts and, at degenerate
+ * optima, x and y may therefore differ from independent solves; statuses and
+ * optima do not.  Needs m + 2 <= 112 and
  * n + n_art + 1 <= 112 (n_art = rows whose "<=" form has a negative rhs),
- * else BLP_ERR_TOO_LARGE.  Reads b and sense back to the host once
- * (synchronising the stream); the solve itself is ordered on the stream.
+ * else BLP_ERR_TOO_LARGE.  Reads b, sense and the first 65 objectives back
+ * to the host once (synchronising the stream); the solve itself is ordered
+ * on the stream.
  * The handle keeps no results of this call (blp_backward and
  * blp_get_solution refer to the last blp_solve_batch). */
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,

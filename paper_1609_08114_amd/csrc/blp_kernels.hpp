@@ -51,6 +51,7 @@ struct KParams {
     int32_t bin;
     int32_t direct;       // 1: entry = direct_first + blockIdx.x, no queue
     int64_t chunk;        // shared-constraint mode: LPs taken per queue pop
+    int32_t shared_in;    // 1: every LP reads A, b and sense at offset 0 (one shared constraint set)
     int64_t direct_first;
     // streaming kernel workspace: one slot of ws_slot doubles per workgroup
     double* ws;
@@ -140,16 +141,24 @@ __device__ __forceinline__ int pack_id(int id, int pos) { return id == ID_NONE ?
 __device__ __forceinline__ int unpack_id(int p) { return p == PACK_NONE ? ID_NONE : (p >> 16); }
 __device__ __forceinline__ int unpack_pos(int p) { return p == PACK_NONE ? -1 : (p & 0xffff); }
 
-// Value of the DPP source lane, lanes outside row mask RM keeping their own.
+// Value of the DPP source lane.  With every row enabled (RM = 0xF) the
+// controls used here read a valid lane for every lane, so no "old" value is
+// needed and the move can fold into its consumer; with a partial row mask the
+// disabled rows keep their own value.
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dpp_i32(int v) {
+    if constexpr (RM == 0xF)
+        return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+    else
+        return __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xF, false);
+}
 template <int CTRL, int RM = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, RM, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, RM, 0xF, false);
-    return __hiloint2double(hi, lo);
+    return __hiloint2double(dpp_i32<CTRL, RM>(__double2hiint(v)), dpp_i32<CTRL, RM>(__double2loint(v)));
 }
 template <int CTRL, int RM = 0xF>
 __device__ __forceinline__ int dpp_min_i32(int v) {
-    const int o = __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xF, false);
+    const int o = dpp_i32<CTRL, RM>(v);
     return o < v ? o : v;
 }
 

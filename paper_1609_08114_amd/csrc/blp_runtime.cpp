@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -700,12 +701,29 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need m + 2 <= %d and n + n_art + 1 <= %d", rows, cols);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    // the tableau width depends on how many rows need an artificial variable
+    // the tableau width depends on how many rows need an artificial variable;
+    // the first objectives tell whether consecutive directions are close
+    // enough for warm starts
     std::vector<double> hb(m);
     std::vector<int8_t> hs(m);
+    const int64_t ns = std::min<int64_t>(count, 65);
+    std::vector<double> hc((size_t)std::max<int64_t>(ns, 1) * n);
     HIP_TRY(h, hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipMemcpyAsync(hs.data(), sense, (size_t)m, hipMemcpyDeviceToHost, s));
+    if (ns > 0) HIP_TRY(h, hipMemcpyAsync(hc.data(), C, sizeof(double) * ns * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
+    int close = 0;
+    for (int64_t k = 1; k < ns; ++k) {
+        double dot = 0.0, aa = 0.0, bb = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double u = hc[(size_t)k * n + j], v = hc[(size_t)(k - 1) * n + j];
+            dot += u * v;
+            aa += u * u;
+            bb += v * v;
+        }
+        close += dot > 0.9 * std::sqrt(aa * bb);
+    }
+    const bool warm = ns > 1 && 2 * close >= ns - 1;
     int nart = 0;
     for (int i = 0; i < m; ++i) nart += (hs[i] ? -hb[i] : hb[i]) < 0.0;
     if (n + nart + 1 > cols)
@@ -740,6 +758,18 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     HIP_TRY(h, h->shared_ctr.reserve(sizeof(int32_t) * 64));
     P.bin_head = h->shared_ctr.as<int32_t>();
     P.bin = 0;
+    if (!warm) {
+        // unrelated directions: every objective is a cold solve, by the
+        // register kernel of the same tile, reading the one constraint set
+        int v = -1;
+        for (int i = 0; i < h->nreg; ++i)
+            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols) v = i;
+        if (v < 0) return fail(h, BLP_ERR_STATE, "no register variant of the shared tile shape");
+        P.shared_in = 1;
+        HIP_TRY(h, launch_reset(P.bin_head, 1, s));
+        HIP_TRY(h, h->variants[v].launch(P, (int)std::min<int64_t>(h->reg_workers[v], count), s));
+        return BLP_SUCCESS;
+    }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, shared_kernel_ptr(), shared_threads(), 0) != hipSuccess ||
         occ < 1)

@@ -190,6 +190,8 @@ simplex_blk_kernel(KParams P) {
     // group partial sums of the rebuilt objective row, the chunk being served
     __shared__ double s_cb[SH ? RP : 1], s_part[SH ? GR * CP : 1];
     __shared__ int64_t s_cur, s_end;
+    __shared__ int s_pending;      // SH: objective handed back to a cold start
+    __shared__ double s_sim[3 * NW];  // SH: per-wave sums for the similarity test
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -204,24 +206,34 @@ simplex_blk_kernel(KParams P) {
     const int64_t len = work_len(P);
     bool first = true;
     unsigned dead = 0;  // bit q: row q*64 + lane is redundant
-    if (SH && t == 0) s_cur = s_end = 0;
+    if (SH && t == 0) {
+        s_cur = s_end = 0;
+        s_pending = -1;
+    }
     // next LP index of this workgroup (-1: none); SH takes chunks
     auto pop = [&]() __attribute__((always_inline)) -> int {
         if (t == 0) {
-            int64_t q;
-            if (SH) {
-                if (s_cur >= s_end) {
-                    const int64_t c0 = (int64_t)atomicAdd(P.bin_head + P.bin, 1) * P.chunk;
-                    s_cur = c0 < len ? c0 : len;
-                    s_end = c0 + P.chunk < len ? c0 + P.chunk : len;
-                }
-                q = s_cur < s_end ? s_cur++ : len;
-            } else if (P.direct) {
-                q = first ? P.direct_first + (int64_t)blockIdx.x : len;
+            int kk;
+            if (SH && s_pending >= 0) {  // an objective handed back for a cold start
+                kk = s_pending;
+                s_pending = -1;
             } else {
-                q = atomicAdd(P.bin_head + P.bin, 1);
+                int64_t q;
+                if (SH) {
+                    if (s_cur >= s_end) {
+                        const int64_t c0 = (int64_t)atomicAdd(P.bin_head + P.bin, 1) * P.chunk;
+                        s_cur = c0 < len ? c0 : len;
+                        s_end = c0 + P.chunk < len ? c0 + P.chunk : len;
+                    }
+                    q = s_cur < s_end ? s_cur++ : len;
+                } else if (P.direct) {
+                    q = first ? P.direct_first + (int64_t)blockIdx.x : len;
+                } else {
+                    q = atomicAdd(P.bin_head + P.bin, 1);
+                }
+                kk = q < len ? (int)work_item(P, q) : -1;
             }
-            s_k = q < len ? (int)work_item(P, q) : -1;
+            s_k = kk;
             s_bad = 0;
         }
         first = false;
@@ -236,7 +248,7 @@ simplex_blk_kernel(KParams P) {
         // ------------------------------------------------------------ load
         LpRef L = lp_ref(P, k);
         LpRef Lin = L;  // where the constraint data are read
-        if (SH) Lin.a_off = Lin.row_off = 0;
+        if (SH || P.shared_in) Lin.a_off = Lin.row_off = 0;
         const int m = L.m, n = L.n;
         if (m > RP - 2 || n + 1 > CP) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
@@ -412,6 +424,41 @@ simplex_blk_kernel(KParams P) {
                 if (k < 0) break;
                 L = lp_ref(P, k);
                 if (same) continue;
+                {
+                    // warm start only if the new objective points close to the
+                    // previous one (cosine > 0.9); otherwise the previous basis
+                    // is usually farther from the new optimum than the slack
+                    // basis, and the objective goes back to a cold start
+                    double dot = 0.0, nn = 0.0, oo = 0.0;
+                    for (int j = t; j < n; j += NT) {
+                        const double cn = P.c[L.col_off + j], co = s_c[j];
+                        dot += cn * co;
+                        nn += cn * cn;
+                        oo += co * co;
+                    }
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        dot += __shfl_xor(dot, o);
+                        nn += __shfl_xor(nn, o);
+                        oo += __shfl_xor(oo, o);
+                    }
+                    if (lane == 0) {
+                        s_sim[3 * (t >> 6)] = dot;
+                        s_sim[3 * (t >> 6) + 1] = nn;
+                        s_sim[3 * (t >> 6) + 2] = oo;
+                    }
+                    __syncthreads();
+                    dot = nn = oo = 0.0;
+                    for (int w = 0; w < NW; ++w) {
+                        dot += s_sim[3 * w];
+                        nn += s_sim[3 * w + 1];
+                        oo += s_sim[3 * w + 2];
+                    }
+                    if (!(dot > 0.9 * sqrt(nn * oo))) {  // also taken for non-finite c
+                        if (t == 0) s_pending = k;
+                        __syncthreads();
+                        break;
+                    }
+                }
                 int badc = 0;
                 for (int j = t; j < n; j += NT) {
                     const double cj = P.c[L.col_off + j];
@@ -556,6 +603,7 @@ simplex_blk_kernel(KParams P) {
             BLP_T(t_p1);
             // publish the entering column (f) and clear its slot; the slot
             // becomes the leaving variable's column
+            const int e_piv = e;  // Step 1 of the next pivot overwrites e before the update
             {
                 const int ce = __builtin_amdgcn_readfirstlane(e / GC), te = e % GC;
                 if (tcb == te) {
@@ -565,7 +613,7 @@ simplex_blk_kernel(KParams P) {
 #pragma unroll
                             for (int r = 0; r < RB; ++r) {
                                 s_f[buf][i0 + r] = T[r][c];
-                                T[r][c] = 0.0;
+                                if (!SH) T[r][c] = 0.0;
                             }
                         }
                 }
@@ -582,7 +630,7 @@ simplex_blk_kernel(KParams P) {
                 l = ratio_regs(m, lane, P.eps_piv, fr, bR, bs, dead, rmin, lv);
                 if (l < 0) {
                     st = mode == 2 ? ST_UNBOUNDED : ST_NUMERICAL;
-                    if (SH) continue;
+                    if (SH) continue;  // the tile is untouched (SH clears the slot at the update)
                     break;
                 }
             }
@@ -608,9 +656,15 @@ simplex_blk_kernel(KParams P) {
             __syncthreads();
             BLP_T(t_p3);
             double nf[RB], pc[CB];
-            const int dl = l - i0;  // row i0 + r is l iff r == dl
 #pragma unroll
-            for (int r = 0; r < RB; ++r) nf[r] = r == dl ? 0.0 : -s_f[buf][i0 + r];
+            for (int r = 0; r < RB; ++r) nf[r] = -s_f[buf][i0 + r];
+            // only the wave holding row l: its coefficient is +0
+            constexpr int ROWS_PER_WAVE = 64 / GC * RB;
+            if (t / 64 == l / ROWS_PER_WAVE) {
+                const int dl = l - i0;  // row i0 + r is l iff r == dl
+#pragma unroll
+                for (int r = 0; r < RB; ++r) nf[r] = r == dl ? 0.0 : nf[r];
+            }
 #pragma unroll
             for (int c = 0; c < CB; ++c) pc[c] = s_p[buf][c * GC + tcb];
             // Step 3 on the mirrors
@@ -625,7 +679,8 @@ simplex_blk_kernel(KParams P) {
                         const double pj = s_p[buf][j];
                         const bool ent = q * 64 == el;
                         dO[q] = __builtin_fma(-fO, pj, ent ? 0.0 : dO[q]);
-                        dW[q] = __builtin_fma(-fW, pj, ent ? 0.0 : dW[q]);
+                        // the phase-1 row is read only in phase 1 and drive-out
+                        if (mode != 2) dW[q] = __builtin_fma(-fW, pj, ent ? 0.0 : dW[q]);
                         cv[q] = ent ? lv : cv[q];
                     }
                 }
@@ -640,6 +695,18 @@ simplex_blk_kernel(KParams P) {
             if (mode != 3) {
                 degen = rmin == 0.0 ? degen + 1 : 0;
                 step1();  // next pivot's entering column, overlapping the update below
+            }
+            if (SH) {  // clear the entering slot here, once the pivot is certain
+                const int ce = __builtin_amdgcn_readfirstlane(e_piv / GC), te = e_piv % GC;
+                if (tcb == te) {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        if (c == ce) {
+#pragma unroll
+                            for (int r = 0; r < RB; ++r)
+                                if (i0 + r != l) T[r][c] = 0.0;
+                        }
+                }
             }
             // Step 3 on the tile; the pivot row keeps p (fma(+0, p, p) = p)
 #pragma unroll

@@ -246,7 +246,12 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 const int i = lane + 64 * q;
                 nf[q] = i < ld ? -S.f[i] : 0.0;
             }
+            // In phase 2 a slot holding an artificial variable never enters
+            // again and feeds no output (pricing skips it, duals come from
+            // the logical columns), so its column is not streamed.
+            const bool skip_art = mode == 2;
             for (int j = wave; j < C; j += NW) {
+                if (skip_art && S.colvar[j] >= id_lim && j != RHS) continue;
                 const double pj = S.p[j];
                 const bool je = j == e;
                 double v[QM];

@@ -110,6 +110,12 @@ def test_type2_polytope_phase1_once():
     C = G / np.linalg.norm(G, axis=1, keepdims=True)
     g, o, _ = _check(A, b, sense, C, "type2")
     assert (o["status"] == oracle.OPTIMAL).all()
+    # the same polytope swept around a circle: warm starts after one phase 1
+    u, v = rng.normal(size=(2, n))
+    t = np.linspace(0.0, 2.0 * np.pi, 600, endpoint=False)
+    Cs = np.cos(t)[:, None] * u + np.sin(t)[:, None] * v
+    g, o, _ = _check(A, b, sense, Cs, "type2-sweep")
+    assert g["iters"].mean() < 0.5 * o["iters"].mean()
 
 
 def test_mixed_outcomes_and_bad_objectives():
@@ -129,12 +135,34 @@ def test_mixed_outcomes_and_bad_objectives():
     assert set(np.unique(st)) >= {oracle.OPTIMAL, oracle.UNBOUNDED}
 
 
+def test_mixed_outcomes_along_a_sweep():
+    # warm starts through optimal and unbounded objectives, one of them NaN
+    A = np.array([[1.0, -1.0, 0.0], [-1.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 1.0, 1.0]])
+    b = np.array([2.0, 3.0, 5.0, 1.0])
+    sense = np.array([0, 0, 0, 1], np.int8)
+    t = np.linspace(0.0, 4.0 * np.pi, 800, endpoint=False)
+    C = np.stack([np.cos(t), np.sin(t), 0.3 + 0.2 * np.cos(3 * t)], axis=1)
+    C[401, 0] = np.nan
+    g = _shared_gpu(A, b, sense, C)
+    assert g["status"][401] == oracle.NUMERICAL
+    keep = np.ones(len(C), bool)
+    keep[401] = False
+    g2, o, _ = _check(A, b, sense, C[keep], "mixed-sweep")
+    assert set(np.unique(o["status"])) >= {oracle.OPTIMAL, oracle.UNBOUNDED}
+    # the statuses of the full run agree with the run without the NaN objective
+    assert np.array_equal(g["status"][keep], g2["status"])
+
+
 def test_infeasible_constraints():
     A = np.array([[1.0, 1.0], [1.0, 1.0]])
     b = np.array([1.0, 3.0])
     sense = np.array([0, 1], np.int8)
     C = np.random.default_rng(2).normal(size=(50, 2))
     g, o, _ = _check(A, b, sense, C, "infeasible")
+    assert (g["status"] == oracle.INFEASIBLE).all()
+    t = np.linspace(0.0, 1.0, 200)
+    Cs = np.stack([1.0 + 0.1 * t, 1.0 - 0.1 * t], axis=1)  # close directions: the warm-start kernel
+    g, o, _ = _check(A, b, sense, Cs, "infeasible-sweep")
     assert (g["status"] == oracle.INFEASIBLE).all()
 
 
