@@ -31,6 +31,7 @@ const RegVariant* reg_variants(int* count);
     BLP_REG_VARIANT("w2_r64_c64",    2, 2,  32, 1)           \
     BLP_REG_VARIANT("w4_r128_c112",  4, 2,  56, 2)           \
     BLP_BLK_VARIANT("b4_r112_c112",  4, 16, 7, 7, 2)         \
+    BLP_BLK_VARIANT("b8_r160_c160",  8, 16, 5, 10, 2)        \
     BLP_REG_VARIANT("w8_r128_c128",  8, 4,  32, 2)
 // clang-format on
 
