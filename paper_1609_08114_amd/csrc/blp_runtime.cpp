@@ -278,7 +278,10 @@ struct SolvePlan {
 };
 
 // Validation, outputs, metadata upload, workspace sizing.  No kernel launch.
-static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp) {
+// stream_all: size the streaming workspace as if every simplex LP could reach
+// the streaming kernel (the autotuner times it on register-variant samples).
+static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp,
+                         bool stream_all = false) {
     const int64_t K = B->count;
     if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
     const bool uni = B->uniform != 0;
@@ -289,6 +292,21 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     bool any_simplex = false, any_box = false;
     int64_t n_box = 0, tot_a = 0, tot_m = 0, tot_n = 0;
     int max_m = 0, max_cols = 0;
+    int64_t max_slot = 0;       // largest streaming tableau (ldk x (n + m + 1) doubles)
+    int64_t n_may_stream = 0;   // simplex LPs no register variant is sure to hold
+    const bool remap_streams = [&] {
+        for (int v = 0; v < h->nreg; ++v)
+            if (h->remap[v] >= h->nreg) return true;
+        return false;
+    }();
+    auto sure_register = [&](int m, int n) {
+        if (stream_all || h->opt.variant == -2 || remap_streams) return false;
+        for (int v = 0; v < h->nreg; ++v) {
+            if (h->opt.variant >= 0 && v != h->opt.variant) continue;
+            if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + m + 1) return true;
+        }
+        return false;
+    };
     for (int64_t k = 0; k < nmeta; ++k) {
         const int m = h->h_m[k], n = h->h_n[k], kd = h->h_kind[k];
         if (kd == BLP_KIND_SIMPLEX) {
@@ -299,6 +317,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             any_simplex = true;
             max_m = std::max(max_m, m);
             max_cols = std::max(max_cols, n + m + 1);
+            max_slot = std::max<int64_t>(max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
+            if (!sure_register(m, n)) ++n_may_stream;
         } else if (kd == BLP_KIND_HYPERBOX) {
             if (m != 0 || n < 1) return fail(h, BLP_ERR_ARG, "LP %lld: hyperbox LP needs m == 0 and n >= 1", (long long)k);
             any_box = true;
@@ -311,6 +331,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         tot_n += n;
     }
     if (uni) {
+        n_may_stream *= K;
         n_box *= K;
         tot_a *= K;
         tot_m *= K;
@@ -469,8 +490,10 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             occ < 1)
             occ = 1;
         if (h->opt.workers_per_cu > 0) occ = std::min(occ, (int)h->opt.workers_per_cu);
-        sp.gm_workers = occ * h->cu_count;
-        const size_t slot = (size_t)sp.gm_ld * sp.gm_cols;
+        // one workspace slot per streaming workgroup, no more workgroups
+        // than LPs that can reach the streaming kernel
+        sp.gm_workers = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * h->cu_count, n_may_stream));
+        const size_t slot = (size_t)max_slot;
         HIP_TRY(h, h->ws.reserve(sizeof(double) * slot * (size_t)sp.gm_workers));
         P.ws = h->ws.as<double>();
         P.ws_slot = (int64_t)slot;
@@ -1071,7 +1094,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
     const int saved_force = h->opt.variant;
     h->opt.variant = -1;
     SolvePlan sp;
-    blp_error e = prepare(h, B, nullptr, s, sp);
+    blp_error e = prepare(h, B, nullptr, s, sp, /*stream_all=*/true);
     if (e == BLP_SUCCESS) e = enqueue_binning(h, sp, s);
     h->opt.variant = saved_force;
     if (e != BLP_SUCCESS || sp.box_only_uniform) {

@@ -1,6 +1,7 @@
 // Streaming simplex kernel for tableaux too large for a workgroup's
 // registers: one LP per workgroup, the condensed tableau in a per-workgroup
-// HBM workspace slot, column-major (element (i, j) at ws[j*ld + i]) so that
+// HBM workspace slot, column-major (element (i, j) at ws[j*ldk + i], ldk =
+// m + 2 rounded up to 16 for this LP) so that
 // the column operations of Steps 2 and 3 are coalesced (Sec. 4.3).  Each
 // pivot streams the whole tableau once (read + write), which is the
 // HBM/L2-bound part; Step 1 and Step 2 run on LDS mirrors of the active
@@ -55,9 +56,6 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double* const Tg = P.ws + (int64_t)blockIdx.x * P.ws_slot;
-    const int ROW_OBJ = ld - 1, ROW_W = ld - 2;
-    // workspace index of tableau cell (i, j)
-    auto at = [&](int i, int j) -> int64_t { return RM ? (int64_t)i * cg_max + j : (int64_t)j * ld + i; };
 
     const int64_t len = work_len(P);
     bool first = true;
@@ -95,6 +93,11 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
         __syncthreads();
         const int nart = s_nart;
         const int C = n + nart + 1, RHS = C - 1;
+        // this LP's tableau: ldk rows (m + 2 rounded up to 16) by C columns
+        const int ldk = ((m + 2 + 15) / 16) * 16;
+        const int ROW_OBJ = ldk - 1, ROW_W = ldk - 2;
+        // workspace index of tableau cell (i, j)
+        auto at = [&](int i, int j) -> int64_t { return RM ? (int64_t)i * C + j : (int64_t)j * ldk + i; };
         if (m > ld - 2 || C > cg_max) {
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
             __syncthreads();
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
         // the other cells, column by column
         for (int j = wave; j < C; j += NW) {
             const int sur_row = (j >= n && j < RHS) ? S.artrow[j - n] : -1;
-            for (int i = lane; i < ld; i += 64) {
+            for (int i = lane; i < ldk; i += 64) {
                 if (i < m && j < n) continue;  // written above
                 double v = 0.0;
                 if (i < m) {
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             for (int j = t; j < C; j += NT) S.d[j] = Tg[at(row, j)];
         };
         mirror_row(phase == 1 ? ROW_W : ROW_OBJ);
-        for (int i = t; i < ld; i += NT) S.b[i] = Tg[at(i, RHS)];
+        for (int i = t; i < ldk; i += NT) S.b[i] = Tg[at(i, RHS)];
         __syncthreads();
         const double w0 = S.b[ROW_W];
         const int max_iter = P.max_iter > 0 ? P.max_iter : 50 * (m + n);
@@ -224,7 +227,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 }
             }
             // entering column -> LDS
-            for (int i = t; i < ld; i += NT) S.f[i] = Tg[at(i, e)];
+            for (int i = t; i < ldk; i += NT) S.f[i] = Tg[at(i, e)];
             __syncthreads();
             if (mode != 3) {
                 l = ratio_test(m, lane, P.eps_piv, S.f, S.b, S.basis, S.flag, rmin);
@@ -244,7 +247,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 const int i = lane + 64 * q;
-                nf[q] = i < ld ? -S.f[i] : 0.0;
+                nf[q] = i < ldk ? -S.f[i] : 0.0;
             }
             // In phase 2 a slot holding an artificial variable never enters
             // again and feeds no output (pricing skips it, duals come from
@@ -258,12 +261,12 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
                     const int i = lane + 64 * q;
-                    v[q] = (i < ld && !je) ? Tg[at(i, j)] : 0.0;
+                    v[q] = (i < ldk && !je) ? Tg[at(i, j)] : 0.0;
                 }
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
                     const int i = lane + 64 * q;
-                    if (i < ld) {
+                    if (i < ldk) {
                         double w = __builtin_fma(nf[q], pj, v[q]);
                         w = i == l ? pj : w;
                         Tg[at(i, j)] = w;
