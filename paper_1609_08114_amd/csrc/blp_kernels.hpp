@@ -70,9 +70,14 @@ struct KParams {
 
 // Optional in-kernel phase timers (s_memtime cycles of wave 0, summed over
 // workgroups): build with -DBLP_PHASE_TIMERS.  Slots: 0 load, 1 price,
-// 2 entering-column publish, 3 ratio test, 4 pivot update, 5 extraction,
-// 6 pivots, 7 LPs.
-enum { TM_LOAD = 0, TM_PRICE, TM_PUBCOL, TM_RATIO, TM_PIVOT, TM_EXTRACT, TM_PIVOTS, TM_LPS, TM_SLOTS };
+// 2 entering-column publish, 3 ratio test + pivot-row division + barrier,
+// 4 pivot update, 5 extraction, 6 pivots, 7 LPs; block-tile kernel only:
+// 8 ratio test alone, 9 pivot-row division in the owning wave, 10 pivots
+// whose row wave 0 owns.
+enum {
+    TM_LOAD = 0, TM_PRICE, TM_PUBCOL, TM_RATIO, TM_PIVOT, TM_EXTRACT, TM_PIVOTS, TM_LPS,
+    TM_RTEST, TM_DIV, TM_DIVN, TM_SLOTS
+};
 #ifdef BLP_PHASE_TIMERS
 #define BLP_TDECL unsigned long long tm_acc_[TM_SLOTS] = {}
 #define BLP_T(v) const unsigned long long v = __builtin_readcyclecounter()

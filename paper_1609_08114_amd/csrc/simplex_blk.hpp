@@ -81,7 +81,7 @@ __device__ __forceinline__ void price_rpc_regs(int nslots, int lane, int id_lim,
                 for (int s = 0; s < target; ++s) mask &= mask - 1;  // drop the lowest set bits
                 const int src = __ffsll((long long)mask) - 1;
                 e_pos = q * 64 + src;
-                e_id = __shfl(cv[q], src);
+                e_id = __builtin_amdgcn_readlane(cv[q], src);  // uniform: keeps the pivot loop's branches scalar
             } else {
                 target -= cnt;
             }
@@ -105,8 +105,11 @@ __device__ __forceinline__ int ratio_regs(int m, int lane, double eps_piv, const
         const double a = f[q];
         const bool cand = (i < m) & !((dead >> q) & 1u) & (a > eps_piv);
         const double bi = b[q];
-        // the division only where it is a candidate (no spurious inf/nan work)
-        const double ratio = bi <= 0.0 ? 0.0 : bi / (cand ? a : 1.0);
+        // every lane divides (by 1 where it is no candidate): no branch, so
+        // the chains of all RS rows interleave
+        double ratio = bi / (cand ? a : 1.0);
+        __asm__("" : "+v"(ratio));
+        ratio = bi <= 0.0 ? 0.0 : ratio;
         const double key = -ratio;
         const bool take = cand & ((key > bk) | ((key == bk) & (bs[q] < bid)));
         bk = take ? key : bk;
@@ -123,22 +126,17 @@ __device__ __forceinline__ int ratio_regs(int m, int lane, double eps_piv, const
 // division) and b_ok = |b| in [2^-500, 2^500]: q = x y is within one ulp of
 // x / b, the residual x - b q is exact in one FMA, and q + residual * y
 // rounded once is the correctly rounded quotient (Markstein's theorem, IBM J.
-// Res. Dev. 34(1), 1990).  Outside the range where no step can overflow or
-// underflow, and for x = 0 (sign of zero), the plain division or the product
-// is used instead, so the result always equals x / b.
-__device__ __forceinline__ double div_rn(double x, double b, double y, bool b_ok) {
+// Res. Dev. 34(1), 1990).  x = 0 takes the product (sign of zero).  `ok` is
+// false where a step could overflow or underflow (|x| outside [2^-500,
+// 2^500] or b outside its range); the caller then divides instead, so the
+// result always equals x / b.  No branch here: a row's entries form one
+// block of independent chains.
+__device__ __forceinline__ double div_rn_fast(double x, double b, double y, bool b_ok, bool& ok) {
     const double q = x * y;
     const double ax = fabs(x);
     const bool zero = x == 0.0;
-    const bool fast = zero | (b_ok & (ax >= 0x1p-500) & (ax <= 0x1p500));
-    double p = zero ? q : __builtin_fma(__builtin_fma(-b, q, x), y, q);
-    if (!fast) {
-        // never taken on ordinary data; the empty volatile asm keeps the
-        // compiler from evaluating the division on every call
-        __asm__ volatile("");
-        p = x / b;
-    }
-    return p;
+    ok = zero | (b_ok & (ax >= 0x1p-500) & (ax <= 0x1p500));
+    return zero ? q : __builtin_fma(__builtin_fma(-b, q, x), y, q);
 }
 
 // Wave-uniform value of a mirror entry (row or slot `idx`).
@@ -181,7 +179,9 @@ simplex_blk_kernel(KParams P) {
     constexpr int RS = (RP + 63) / 64, CS = (CP + 63) / 64;
     static_assert(GR * GC == NT && 64 % GC == 0 && RP >= 4 && CP >= 2 && RS <= 32, "bad block tile");
 
-    __shared__ double s_f[2][RP], s_p[2][CP];
+    // pivot column / pivot row, padded to whole waves so that every lane
+    // reads its mirror entries without a bounds branch
+    __shared__ double s_f[2][RS * 64], s_p[2][CS * 64];
     __shared__ double s_sig[RP], s_b[RP], s_c[CP], s_w[CP];
     __shared__ int s_colvar[CP], s_basis[RP], s_artrow[RP], s_rank[RP];
     __shared__ unsigned char s_flag[RP];
@@ -238,7 +238,7 @@ simplex_blk_kernel(KParams P) {
         }
         first = false;
         __syncthreads();
-        return s_k;
+        return __builtin_amdgcn_readfirstlane(s_k);
     };
     for (;;) {
         int k = pop();
@@ -276,7 +276,7 @@ simplex_blk_kernel(KParams P) {
         __syncthreads();
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
         __syncthreads();
-        const int nart = s_nart;
+        const int nart = __builtin_amdgcn_readfirstlane(s_nart);
         if (n + nart + 1 > CP) {
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
             __syncthreads();
@@ -624,7 +624,8 @@ simplex_blk_kernel(KParams P) {
 #pragma unroll
             for (int q = 0; q < RS; ++q) {
                 const int i = q * 64 + lane;
-                fr[q] = i < RP ? s_f[buf][i] : 0.0;
+                const double v = s_f[buf][i];
+                fr[q] = i < RP ? v : 0.0;
             }
             if (mode != 3) {
                 l = ratio_regs(m, lane, P.eps_piv, fr, bR, bs, dead, rmin, lv);
@@ -635,35 +636,68 @@ simplex_blk_kernel(KParams P) {
                 }
             }
             const double pe = mirror_at(fr, l);
-            // Step 3's new pivot row, divided by the owners of row l
-            if (trb == l / RB) {
-                const int rl = __builtin_amdgcn_readfirstlane(l % RB);
+            BLP_T(t_p2b);
+            BLP_TACC(TM_RTEST, t_p2, t_p2b);
+            // Step 3's new pivot row.  The owners of row l (GC lanes of one
+            // wave) put its entries into s_p[buf] and zero them in the tile;
+            // the whole wave holding row l then divides CS entries per lane
+            // (LDS operations of one wave complete in order, so no barrier
+            // is needed between the two).  After the update the tile's row l
+            // is fma(1, p, 0) = p.
+            constexpr int ROWS_PER_WAVE = 64 / GC * RB;
+            const bool row_wave = t / 64 == l / ROWS_PER_WAVE;
+            if (row_wave) {
+                if (trb == l / RB) {
+                    const int rl = __builtin_amdgcn_readfirstlane(l % RB);
+                    const int de = e - tcb;  // slot c*GC + tcb is e iff c*GC == de
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (r == rl) {
+#pragma unroll
+                            for (int c = 0; c < CB; ++c) {
+                                s_p[buf][c * GC + tcb] = c * GC == de ? 1.0 : T[r][c];
+                                T[r][c] = 0.0;
+                            }
+                        }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const double y = 1.0 / pe;
                 const double ape = fabs(pe);
                 const bool pe_ok = ape >= 0x1p-500 && ape <= 0x1p500;
-                const int de = e - tcb;  // slot c*GC + tcb is e iff c*GC == de
+                double xs[CS], ps[CS];
+                bool slow = false;
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r == rl) {
+                for (int q = 0; q < CS; ++q) {
+                    xs[q] = s_p[buf][q * 64 + lane];
+                    bool ok;
+                    ps[q] = div_rn_fast(xs[q], pe, y, pe_ok, ok);
+                    slow |= !ok & (q * 64 + lane < CP);  // padding slots hold no data
+                }
+                if (slow) {  // extreme magnitudes only: the plain division
 #pragma unroll
-                        for (int c = 0; c < CB; ++c) {
-                            const double p = div_rn(c * GC == de ? 1.0 : T[r][c], pe, y, pe_ok);
-                            s_p[buf][c * GC + tcb] = p;
-                            T[r][c] = p;
-                        }
-                    }
+                    for (int q = 0; q < CS; ++q) ps[q] = xs[q] / pe;
+                }
+#pragma unroll
+                for (int q = 0; q < CS; ++q) s_p[buf][q * 64 + lane] = ps[q];
+#ifdef BLP_PHASE_TIMERS
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // the row's LDS writes done
+                BLP_T(t_p2c);
+                BLP_TACC(TM_DIV, t_p2b, t_p2c);
+                BLP_TCOUNT(TM_DIVN, 1ull);
+#endif
             }
             __syncthreads();
             BLP_T(t_p3);
             double nf[RB], pc[CB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) nf[r] = -s_f[buf][i0 + r];
-            // only the wave holding row l: its coefficient is +0
-            constexpr int ROWS_PER_WAVE = 64 / GC * RB;
-            if (t / 64 == l / ROWS_PER_WAVE) {
+            // only the wave holding row l: the pivot row (zeroed) takes 1 * p
+            if (row_wave) {
                 const int dl = l - i0;  // row i0 + r is l iff r == dl
 #pragma unroll
-                for (int r = 0; r < RB; ++r) nf[r] = r == dl ? 0.0 : nf[r];
+                for (int r = 0; r < RB; ++r) nf[r] = r == dl ? 1.0 : nf[r];
             }
 #pragma unroll
             for (int c = 0; c < CB; ++c) pc[c] = s_p[buf][c * GC + tcb];
@@ -672,17 +706,15 @@ simplex_blk_kernel(KParams P) {
                 const double pr = s_p[buf][COL_RHS];
                 const double fO = s_f[buf][ROW_OBJ], fW = s_f[buf][ROW_W];
                 const int el = e - lane, ll = l - lane;  // slot / row q*64 + lane is e / l iff q*64 == el / ll
+                // slots j >= CP (padding lanes) carry values never read
 #pragma unroll
                 for (int q = 0; q < CS; ++q) {
-                    const int j = q * 64 + lane;
-                    if (j < CP) {
-                        const double pj = s_p[buf][j];
-                        const bool ent = q * 64 == el;
-                        dO[q] = __builtin_fma(-fO, pj, ent ? 0.0 : dO[q]);
-                        // the phase-1 row is read only in phase 1 and drive-out
-                        if (mode != 2) dW[q] = __builtin_fma(-fW, pj, ent ? 0.0 : dW[q]);
-                        cv[q] = ent ? lv : cv[q];
-                    }
+                    const double pj = s_p[buf][q * 64 + lane];
+                    const bool ent = q * 64 == el;
+                    dO[q] = __builtin_fma(-fO, pj, ent ? 0.0 : dO[q]);
+                    // the phase-1 row is read only in phase 1 and drive-out
+                    if (mode != 2) dW[q] = __builtin_fma(-fW, pj, ent ? 0.0 : dW[q]);
+                    cv[q] = ent ? lv : cv[q];
                 }
 #pragma unroll
                 for (int q = 0; q < RS; ++q) {
@@ -708,7 +740,7 @@ simplex_blk_kernel(KParams P) {
                         }
                 }
             }
-            // Step 3 on the tile; the pivot row keeps p (fma(+0, p, p) = p)
+            // Step 3 on the tile; the pivot row becomes p (fma(1, p, +0) = p)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
