@@ -34,6 +34,9 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every atomic here is issued by one lane; the wave-aggregating rewrite
+    # would wait for its result at once and defeat the work-list prefetch
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument",
 ]
 

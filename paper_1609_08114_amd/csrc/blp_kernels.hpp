@@ -68,6 +68,16 @@ struct KParams {
     uint64_t seed;
 };
 
+// Workgroup barrier for communication through LDS only: each wave waits for
+// its own LDS operations, not for its global loads and stores, so output
+// stores drain and prefetches stay in flight across it.  The simplex kernels
+// that keep their tableau in registers share data only through LDS.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Optional in-kernel phase timers (s_memtime cycles of wave 0, summed over
 // workgroups): build with -DBLP_PHASE_TIMERS.  Slots: 0 load, 1 price,
 // 2 entering-column publish, 3 ratio test + pivot-row division + barrier,
@@ -165,6 +175,65 @@ template <int CTRL, int RM = 0xF>
 __device__ __forceinline__ int dpp_min_i32(int v) {
     const int o = dpp_i32<CTRL, RM>(v);
     return o < v ? o : v;
+}
+
+// Wave maximum of a signed (hi) or unsigned (lo) dword, valid in lane 63:
+// four in-row DPP steps, then row broadcasts 15 and 31 into rows 1 and 3
+// (the other rows end with unspecified values; only lane 63 is read).  Each
+// step is one max with a DPP operand.
+template <int CTRL, int RM>
+__device__ __forceinline__ int dpp_src(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, RM, 0xF, RM == 0xF);
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+    v = max(v, dpp_src<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+    v = max(v, dpp_src<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+    v = max(v, dpp_src<0x141, 0xF>(v));  // row_half_mirror
+    v = max(v, dpp_src<0x140, 0xF>(v));  // row_mirror
+    v = max(v, dpp_src<0x142, 0xA>(v));  // row_bcast:15
+    v = max(v, dpp_src<0x143, 0xC>(v));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)dpp_src<0xB1, 0xF>((int)v));
+    v = max(v, (unsigned)dpp_src<0x4E, 0xF>((int)v));
+    v = max(v, (unsigned)dpp_src<0x141, 0xF>((int)v));
+    v = max(v, (unsigned)dpp_src<0x140, 0xF>((int)v));
+    v = max(v, (unsigned)dpp_src<0x142, 0xA>((int)v));
+    v = max(v, (unsigned)dpp_src<0x143, 0xC>((int)v));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+    v = min(v, dpp_src<0xB1, 0xF>(v));
+    v = min(v, dpp_src<0x4E, 0xF>(v));
+    v = min(v, dpp_src<0x141, 0xF>(v));
+    v = min(v, dpp_src<0x140, 0xF>(v));
+    v = min(v, dpp_src<0x142, 0xA>(v));
+    v = min(v, dpp_src<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Wave-wide arg-max of 64-bit integer keys (hi signed, lo unsigned: the
+// value hi * 2^32 + lo), ties to the smallest packed (id, pos); the packed
+// winner and its key are returned wave-uniform.  For doubles that are all
+// >= +0 or -inf, the bit pattern is such a key and orders like the double;
+// the bitwise complement of a key reverses the order (a minimum).  Exact
+// ties are rare, so the tie passes run only when the ballot of lanes
+// holding the maximum has more than one lane.  All 64 lanes must be active.
+__device__ __forceinline__ int wave_argmax_i64(int hi, unsigned lo, int pk, int& top_hi, unsigned& top_lo) {
+    top_hi = wave_max_i32(hi);
+    const bool h_eq = hi == top_hi;
+    const uint64_t m1 = __ballot(h_eq);
+    if (__popcll(m1) == 1) {
+        const int w = __ffsll((long long)m1) - 1;
+        top_lo = (unsigned)__builtin_amdgcn_readlane((int)lo, w);
+        return __builtin_amdgcn_readlane(pk, w);
+    }
+    top_lo = wave_max_u32(h_eq ? lo : 0u);
+    const bool eq = h_eq & (lo == top_lo);
+    const uint64_t m2 = __ballot(eq);
+    if (__popcll(m2) == 1) return __builtin_amdgcn_readlane(pk, __ffsll((long long)m2) - 1);
+    return wave_min_i32(eq ? pk : PACK_NONE);
 }
 
 // All 64 lanes must be active.  On return id/pos are wave-uniform.

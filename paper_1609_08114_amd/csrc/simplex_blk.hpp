@@ -45,9 +45,13 @@ __device__ __forceinline__ void price_regs(int nslots, int lane, int id_lim, dou
         bid = take ? v : bid;
         bpos = take ? j : bpos;
     }
-    wave_argmax(bk, bid, bpos);
-    e_id = bid;
-    e_pos = bpos;
+    // bk is -inf or >= +0 (eps_price >= 0), so its bit pattern orders like it
+    const long long kb = __double_as_longlong(bk);
+    int th;
+    unsigned tl;
+    const int pk = wave_argmax_i64((int)(kb >> 32), (unsigned)kb, pack_id(bid, bpos), th, tl);
+    e_id = unpack_id(pk);
+    e_pos = unpack_pos(pk);
 }
 
 // The random-positive-coefficient rule of Sec. 4.2 over register mirrors;
@@ -116,10 +120,15 @@ __device__ __forceinline__ int ratio_regs(int m, int lane, double eps_piv, const
         bid = take ? bs[q] : bid;
         bpos = take ? i : bpos;
     }
-    wave_argmax(bk, bid, bpos);
-    rmin = -bk;
-    leave_id = bid;
-    return bid == ID_NONE ? -1 : bpos;
+    // the lane's smallest ratio (+inf without a candidate) is >= +0: the
+    // complement of its bit pattern orders it largest-first
+    const long long rb = __double_as_longlong(-bk);
+    int th;
+    unsigned tl;
+    const int pk = wave_argmax_i64(~(int)(rb >> 32), ~(unsigned)rb, pack_id(bid, bpos), th, tl);
+    rmin = __longlong_as_double((long long)(((unsigned long long)(unsigned)~th << 32) | (unsigned)~tl));
+    leave_id = unpack_id(pk);
+    return leave_id == ID_NONE ? -1 : unpack_pos(pk);
 }
 
 // x / b rounded to nearest, given y = x / b's reciprocal 1.0 / b (an IEEE
@@ -210,6 +219,11 @@ simplex_blk_kernel(KParams P) {
         s_cur = s_end = 0;
         s_pending = -1;
     }
+    // Persistent work list: when thread 0 takes an LP it also reserves the
+    // next queue position (pf_q); once the LP is loaded it reads that
+    // position's list entry (pf_k, -2 = not read yet).  The atomic and the
+    // list read then overlap the solve instead of preceding the next load.
+    int pf_q = -1, pf_k = -2;
     // next LP index of this workgroup (-1: none); SH takes chunks
     auto pop = [&]() __attribute__((always_inline)) -> int {
         if (t == 0) {
@@ -217,6 +231,13 @@ simplex_blk_kernel(KParams P) {
             if (SH && s_pending >= 0) {  // an objective handed back for a cold start
                 kk = s_pending;
                 s_pending = -1;
+            } else if (!SH && !P.direct) {
+                if (first) {
+                    const int q = atomicAdd(P.bin_head + P.bin, 1);
+                    kk = q < len ? (int)work_item(P, q) : -1;
+                } else {
+                    kk = pf_k != -2 ? pf_k : (pf_q < len ? (int)work_item(P, pf_q) : -1);
+                }
             } else {
                 int64_t q;
                 if (SH) {
@@ -226,18 +247,20 @@ simplex_blk_kernel(KParams P) {
                         s_end = c0 + P.chunk < len ? c0 + P.chunk : len;
                     }
                     q = s_cur < s_end ? s_cur++ : len;
-                } else if (P.direct) {
+                } else {  // one LP per workgroup (grid and one-LP-per-launch modes)
                     q = first ? P.direct_first + (int64_t)blockIdx.x : len;
-                } else {
-                    q = atomicAdd(P.bin_head + P.bin, 1);
                 }
                 kk = q < len ? (int)work_item(P, q) : -1;
             }
             s_k = kk;
             s_bad = 0;
+            if (!SH && !P.direct) {  // reserve the next position (after the LDS write: no wait for it)
+                pf_q = kk >= 0 ? atomicAdd(P.bin_head + P.bin, 1) : (int)len;
+                pf_k = -2;
+            }
         }
         first = false;
-        __syncthreads();
+        lds_barrier();
         return __builtin_amdgcn_readfirstlane(s_k);
     };
     for (;;) {
@@ -252,7 +275,7 @@ simplex_blk_kernel(KParams P) {
         const int m = L.m, n = L.n;
         if (m > RP - 2 || n + 1 > CP) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         int bad = prep_rows<NT>(P, Lin, t, s_sig, s_b, s_flag);
@@ -260,6 +283,8 @@ simplex_blk_kernel(KParams P) {
         // A straight into the tile (scaled below, once the row signs are known)
         // with range-checked buffer loads: the resource covers this LP's m x n
         // block, so rows >= m read as 0; columns >= n get an offset beyond it.
+        // Nothing waits for them before the tile is finished below (the
+        // barriers in between order LDS only).
         {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<double*>(P.A + Lin.a_off), (short)0, m * n * (int)sizeof(double), 0x00020000);
@@ -273,13 +298,13 @@ simplex_blk_kernel(KParams P) {
                         double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(cofs + (unsigned)(r * n) * 8u), 0, 0));
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
-        __syncthreads();
+        lds_barrier();
         const int nart = __builtin_amdgcn_readfirstlane(s_nart);
         if (n + nart + 1 > CP) {
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         // Phase-1 row: for each column, the artificial rows summed in row
@@ -288,9 +313,17 @@ simplex_blk_kernel(KParams P) {
             for (int j = t; j < CP; j += NT) {
                 double acc = 0.0;
                 if (j < n) {
-                    for (int q = 0; q < nart; ++q) {
-                        const int ii = s_artrow[q];
-                        acc = acc + s_sig[ii] * P.A[Lin.a_off + (int64_t)ii * n + j];
+                    // 8 loads in flight, then their terms in row order
+                    for (int q0 = 0; q0 < nart; q0 += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int ii = s_artrow[q0 + u < nart ? q0 + u : q0];
+                            v[u] = P.A[Lin.a_off + (int64_t)ii * n + j];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (q0 + u < nart) acc = acc + s_sig[s_artrow[q0 + u]] * v[u];
                     }
                 } else if (j < n + nart) {
                     acc = -1.0;
@@ -299,7 +332,7 @@ simplex_blk_kernel(KParams P) {
                 }
                 s_w[j] = acc;
             }
-            __syncthreads();
+            lds_barrier();
         }
         // finish the tile with selects only (no divergent branch around the
         // tile): row signs on the A block, +0 beyond it, then the rhs column,
@@ -346,10 +379,10 @@ simplex_blk_kernel(KParams P) {
             bs[q] = i < m ? ((s_flag[i] & RF_ART) ? n + m + i : n + i) : ID_NONE;
         }
         if (bad) atomicOr(&s_bad, 1);
-        __syncthreads();
+        lds_barrier();
         if (s_bad) {
             write_numerical<NT>(P, L, k, t, ST_NUMERICAL);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         const double w0 = mirror_at(bR, ROW_W);
@@ -363,7 +396,7 @@ simplex_blk_kernel(KParams P) {
         // outputs of LP k from the mirrors
         auto extract = [&]() __attribute__((always_inline)) {
             BLP_T(t_x0);
-            __syncthreads();
+            lds_barrier();
             if (t < 64) {
 #pragma unroll
                 for (int q = 0; q < CS; ++q) {
@@ -383,10 +416,10 @@ simplex_blk_kernel(KParams P) {
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
             write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, COL_RHS, s_p[1], s_f[1], s_colvar, s_basis, s_flag, s_p[0],
                               s_f[0]);
-            __syncthreads();
+            lds_barrier();
             BLP_T(t_x1);
             BLP_TACC(TM_EXTRACT, t_x0, t_x1);
             BLP_TCOUNT(TM_PIVOTS, (unsigned long long)iters);
@@ -409,6 +442,7 @@ simplex_blk_kernel(KParams P) {
                 price_regs(COL_RHS, lane, id_lim, P.eps_price, degen >= bland_after, da, cv, e_id, e);
         };
         step1();
+        if (!SH && !P.direct && t == 0 && pf_k == -2) pf_k = pf_q < len ? (int)work_item(P, pf_q) : -1;
         BLP_T(t_load1);
         BLP_TACC(TM_LOAD, t_load0, t_load1);
         for (;;) {
@@ -446,7 +480,7 @@ simplex_blk_kernel(KParams P) {
                         s_sim[3 * (t >> 6) + 1] = nn;
                         s_sim[3 * (t >> 6) + 2] = oo;
                     }
-                    __syncthreads();
+                    lds_barrier();
                     dot = nn = oo = 0.0;
                     for (int w = 0; w < NW; ++w) {
                         dot += s_sim[3 * w];
@@ -455,7 +489,7 @@ simplex_blk_kernel(KParams P) {
                     }
                     if (!(dot > 0.9 * sqrt(nn * oo))) {  // also taken for non-finite c
                         if (t == 0) s_pending = k;
-                        __syncthreads();
+                        lds_barrier();
                         break;
                     }
                 }
@@ -466,10 +500,10 @@ simplex_blk_kernel(KParams P) {
                     s_c[j] = cj;
                 }
                 if (badc) atomicOr(&s_bad, 1);
-                __syncthreads();
+                lds_barrier();
                 if (s_bad) {
                     write_numerical<NT>(P, L, k, t, ST_NUMERICAL);
-                    __syncthreads();
+                    lds_barrier();
                     st = -2;  // written; take the next objective
                     continue;
                 }
@@ -480,7 +514,7 @@ simplex_blk_kernel(KParams P) {
                         if (i < RP) s_cb[i] = (i < m && bs[q] < n) ? s_c[bs[q]] : 0.0;
                     }
                 }
-                __syncthreads();
+                lds_barrier();
                 // partial sums over this thread's rows, in row order
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
@@ -489,7 +523,7 @@ simplex_blk_kernel(KParams P) {
                     for (int r = 0; r < RB; ++r) acc = __builtin_fma(s_cb[i0 + r], T[r][c], acc);
                     s_part[trb * CP + c * GC + tcb] = acc;
                 }
-                __syncthreads();
+                lds_barrier();
                 if (t < 64) {
 #pragma unroll
                     for (int q = 0; q < CS; ++q) {
@@ -502,7 +536,7 @@ simplex_blk_kernel(KParams P) {
                         }
                     }
                 }
-                __syncthreads();
+                lds_barrier();
 #pragma unroll
                 for (int q = 0; q < CS; ++q) {
                     const int j = q * 64 + lane;
@@ -515,7 +549,7 @@ simplex_blk_kernel(KParams P) {
 #pragma unroll
                     for (int c = 0; c < CB; ++c) T[RB - 1][c] = s_p[0][c * GC + tcb];
                 }
-                __syncthreads();
+                lds_barrier();
                 st = -1;
                 iters = 0;
                 degen = 0;
@@ -543,7 +577,7 @@ simplex_blk_kernel(KParams P) {
                 drive_r = r0 + 1;
                 // row r0 into s_p[buf]; the lowest-id non-artificial column
                 // with a usable entry enters
-                __syncthreads();
+                lds_barrier();
                 if (trb == r0 / RB) {
                     const int rr = r0 % RB;
 #pragma unroll
@@ -553,7 +587,7 @@ simplex_blk_kernel(KParams P) {
                             for (int c = 0; c < CB; ++c) s_p[buf][c * GC + tcb] = T[r][c];
                         }
                 }
-                __syncthreads();
+                lds_barrier();
                 double bk = -__builtin_inf();
                 int bid = ID_NONE, bpos = -1;
 #pragma unroll
@@ -569,7 +603,7 @@ simplex_blk_kernel(KParams P) {
                     }
                 }
                 wave_argmax(bk, bid, bpos);
-                __syncthreads();
+                lds_barrier();
                 if (bid == ID_NONE) {  // redundant row
                     if (r0 % 64 == lane) dead |= 1u << (r0 / 64);
                     continue;
@@ -618,7 +652,7 @@ simplex_blk_kernel(KParams P) {
                         }
                 }
             }
-            __syncthreads();
+            lds_barrier();
             BLP_T(t_p2);
             double fr[RS];
 #pragma unroll
@@ -688,7 +722,7 @@ simplex_blk_kernel(KParams P) {
                 BLP_TCOUNT(TM_DIVN, 1ull);
 #endif
             }
-            __syncthreads();
+            lds_barrier();
             BLP_T(t_p3);
             double nf[RB], pc[CB];
 #pragma unroll

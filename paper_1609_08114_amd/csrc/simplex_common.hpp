@@ -70,7 +70,8 @@ __device__ __forceinline__ void scan_art_rows(int m, int lane, const unsigned ch
 }
 
 // Write one LP's outputs.  s_d must hold the objective row (by slot), s_b the
-// rhs column; s_xs (>= n doubles) and s_ys (>= m doubles) are scratch.
+// rhs column; s_xs (>= n doubles) and s_ys (>= m doubles) are scratch.  The
+// barriers order LDS only; the output stores complete asynchronously.
 template <int NT>
 __device__ __forceinline__ void write_outputs(const KParams& P, const LpRef& L, int k, int t, int st, int iters,
                                               int obj_row, int nslots, const double* s_d, const double* s_b,
@@ -79,7 +80,7 @@ __device__ __forceinline__ void write_outputs(const KParams& P, const LpRef& L, 
     const int m = L.m, n = L.n;
     for (int j = t; j < n; j += NT) s_xs[j] = 0.0;
     for (int i = t; i < m; i += NT) s_ys[i] = 0.0;
-    __syncthreads();
+    lds_barrier();
     // x_j = rhs of the row where j is basic; the dual of row i is read from
     // the objective-row entry of its logical variable (zero when basic).
     for (int i = t; i < m; i += NT) {
@@ -90,7 +91,7 @@ __device__ __forceinline__ void write_outputs(const KParams& P, const LpRef& L, 
         const int v = s_colvar[j];
         if (v >= n && v < n + m) s_ys[v - n] = s_d[j];
     }
-    __syncthreads();
+    lds_barrier();
     const double z = -s_b[obj_row];
     if (st == ST_OPTIMAL && !isfinite(z)) st = ST_NUMERICAL;
     const bool nan_out = st == ST_NUMERICAL;
