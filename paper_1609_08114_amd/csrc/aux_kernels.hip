@@ -15,78 +15,123 @@
 namespace blp {
 
 __global__ void reset_bins_kernel(int32_t* counters, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0;
 }
 
-// One wave per LP; per-block bin histogram in LDS, flushed with one atomic
-// per (block, bin) so that a uniform batch does not serialise on one
-// counter.  bins: 0..nreg-1 register variants, nreg streaming, nreg+1
-// hyperbox.
+// Waves take LPs round-robin, two LPs per step so that two sets of row loads
+// are in flight; each block keeps a bin histogram in LDS and adds it to one
+// of kBinStripes copies of the bin counters (stripe = block mod
+// kBinStripes), so that thousands of blocks do not serialise on one address.
+// bins: 0..nreg-1 register variants, nreg streaming, nreg+1 hyperbox.
+// Artificial rows among rows [i0, i0 + 128) of an LP: two wave-widths of
+// rows, loads issued unconditionally (indices clamped into the LP) so that
+// they are all in flight before the first compare.
+struct ArtLoads {
+    double ba, bb;
+    int sa, sb;
+};
+__device__ __forceinline__ ArtLoads art_load(const KParams& P, const LpRef& L, int i0, int lane) {
+    const int ia = min(i0 + lane, L.m - 1), ib = min(i0 + 64 + lane, L.m - 1);
+    return {P.b[L.row_off + ia], P.b[L.row_off + ib], P.sense[L.row_off + ia], P.sense[L.row_off + ib]};
+}
+__device__ __forceinline__ int art_count(const ArtLoads& a, int m, int i0, int lane) {
+    const int ia = i0 + lane, ib = ia + 64;
+    return __popcll(__ballot(ia < m && (a.sa != 0 ? -a.ba : a.ba) < 0.0)) +
+           __popcll(__ballot(ib < m && (a.sb != 0 ? -a.bb : a.bb) < 0.0));
+}
+__device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, int nart) {
+    const int rows = L.m + 2, cols = L.n + nart + 1;
+    int bin = vt.nreg;  // streaming kernel
+    if (vt.force >= 0) {
+        if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols) bin = vt.force;
+    } else if (vt.force == -1) {
+        long best = -1;
+        for (int v = 0; v < vt.nreg; ++v) {
+            if (vt.rows[v] >= rows && vt.cols[v] >= cols) {
+                const long area = (long)vt.rows[v] * vt.cols[v];
+                if (best < 0 || area < best) {
+                    best = area;
+                    bin = v;
+                }
+            }
+        }
+        if (bin < vt.nreg) bin = vt.remap[bin];
+    }
+    return bin;
+}
+
 __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable vt, int32_t* binid,
-                                                        int32_t* bin_count) {
+                                                        int32_t* stripes) {
     __shared__ int hist[kMaxVariants + 2];
-    for (int b = threadIdx.x; b < vt.nreg + 2; b += blockDim.x) hist[b] = 0;
+    const int nbins = vt.nreg + 2;
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < P.count; k += nwaves) {
-        int bin;
-        if (lp_kind(P, k) == 1) {
-            bin = vt.nreg + 1;
-        } else {
-            const LpRef L = lp_ref(P, k);
-            int nart = 0;
-            for (int i0 = 0; i0 < L.m; i0 += 64) {
-                const int i = i0 + lane;
-                bool art = false;
-                if (i < L.m) {
-                    const double bi = P.b[L.row_off + i];
-                    const bool ge = P.sense[L.row_off + i] != 0;
-                    art = (ge ? -bi : bi) < 0.0;
-                }
-                nart += __popcll(__ballot(art));
-            }
-            const int rows = L.m + 2, cols = L.n + nart + 1;
-            bin = vt.nreg;  // streaming kernel
-            if (vt.force >= 0) {
-                if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols) bin = vt.force;
-            } else if (vt.force == -1) {
-                long best = -1;
-                for (int v = 0; v < vt.nreg; ++v) {
-                    if (vt.rows[v] >= rows && vt.cols[v] >= cols) {
-                        const long area = (long)vt.rows[v] * vt.cols[v];
-                        if (best < 0 || area < best) {
-                            best = area;
-                            bin = v;
-                        }
-                    }
-                }
-                if (bin < vt.nreg) bin = vt.remap[bin];
-            }
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform: scalar branches below
+    for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; k < P.count; k += 2 * nwaves) {
+        // two LPs per step (the second may be absent or a hyperbox): the
+        // first 128 rows of both are loaded before either is counted
+        const int64_t k2 = k + nwaves < P.count ? k + nwaves : k;
+        const bool s1 = lp_kind(P, k) != 1, s2 = lp_kind(P, k2) != 1;
+        const LpRef L1 = lp_ref(P, k), L2 = lp_ref(P, k2);
+        int n1 = 0, n2 = 0;
+        if (s1 || s2) {
+            // a hyperbox slot borrows the other LP's rows (loaded, not counted)
+            const ArtLoads a1 = art_load(P, s1 ? L1 : L2, 0, lane);
+            const ArtLoads a2 = art_load(P, s2 ? L2 : L1, 0, lane);
+            n1 = s1 ? art_count(a1, L1.m, 0, lane) : 0;
+            n2 = s2 ? art_count(a2, L2.m, 0, lane) : 0;
         }
+        for (int i0 = 128; s1 && i0 < L1.m; i0 += 128) n1 += art_count(art_load(P, L1, i0, lane), L1.m, i0, lane);
+        for (int i0 = 128; s2 && i0 < L2.m; i0 += 128) n2 += art_count(art_load(P, L2, i0, lane), L2.m, i0, lane);
+        const int b1 = s1 ? bin_of(vt, L1, n1) : vt.nreg + 1;
+        const int b2 = k2 != k ? (s2 ? bin_of(vt, L2, n2) : vt.nreg + 1) : -1;
         if (lane == 0) {
-            binid[k] = bin;
-            atomicAdd(&hist[bin], 1);
+            binid[k] = b1;
+            atomicAdd(&hist[b1], 1);
+            if (b2 >= 0) {
+                binid[k2] = b2;
+                atomicAdd(&hist[b2], 1);
+            }
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < vt.nreg + 2; b += blockDim.x)
-        if (hist[b]) atomicAdd(bin_count + b, hist[b]);
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (hist[b]) atomicAdd(stripes + b * kBinStripes + (blockIdx.x % kBinStripes), hist[b]);
 }
 
-__global__ void bin_offsets_kernel(const int32_t* bin_count, int32_t* bin_off, int nbins) {
+// Bin sizes (the kBinStripes copies summed) and their exclusive prefix: wave
+// w sums bins w, w + 4, ..., one stripe per lane.
+__global__ void __launch_bounds__(256) bin_offsets_kernel(const int32_t* stripes, int32_t* bin_count,
+                                                          int32_t* bin_off, int nbins) {
+    static_assert(kBinStripes == 64, "one stripe per lane");
+    __shared__ int total[kMaxVariants + 2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int v[(kMaxVariants + 2 + 3) / 4];
+#pragma unroll
+    for (int u = 0; u < (kMaxVariants + 2 + 3) / 4; ++u) {
+        const int b = wave + 4 * u;
+        v[u] = b < nbins ? stripes[b * kBinStripes + lane] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < (kMaxVariants + 2 + 3) / 4; ++u) {
+        int acc = v[u];
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        const int b = wave + 4 * u;
+        if (lane == 0 && b < nbins) total[b] = acc;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int acc = 0;
         for (int b = 0; b < nbins; ++b) {
+            bin_count[b] = total[b];
             bin_off[b] = acc;
-            acc += bin_count[b];
+            acc += total[b];
         }
     }
 }
 
-// Each block takes a contiguous chunk of LPs, counts its bins in LDS,
-// reserves one range per bin with a single atomic, then writes its entries
-// (in LP order within the block).
 __global__ void __launch_bounds__(256) scatter_kernel(int64_t count, int nbins, const int32_t* binid,
                                                       const int32_t* bin_off, int32_t* bin_fill, int32_t* list) {
     __shared__ int hist[kMaxVariants + 2], base[kMaxVariants + 2];
@@ -266,19 +311,24 @@ __global__ void backward_hyperbox_kernel(KParams P, const double* g, double* dc,
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s) {
-    hipLaunchKernelGGL(reset_bins_kernel, dim3(1), dim3(64), 0, s, counters, n);
+    hipLaunchKernelGGL(reset_bins_kernel, dim3(1), dim3(256), 0, s, counters, n);
     return hipGetLastError();
 }
-hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
-                           hipStream_t s) {
-    int64_t blocks = (P.count + 63) / 64;  // 16 LPs per wave
-    if (blocks > 16384) blocks = 16384;
+int classify_blocks(int64_t count) {
+    int64_t blocks = (count + 15) / 16;  // at least four LPs per wave
+    if (blocks > kClassifyMaxBlocks) blocks = kClassifyMaxBlocks;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, vt, binid, bin_count);
+    return (int)blocks;
+}
+hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* stripes,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)classify_blocks(P.count)), dim3(256), 0, s, P, vt, binid,
+                       stripes);
     return hipGetLastError();
 }
-hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nbins, hipStream_t s) {
-    hipLaunchKernelGGL(bin_offsets_kernel, dim3(1), dim3(64), 0, s, bin_count, bin_off, nbins);
+hipError_t launch_bin_offsets(const int32_t* stripes, int32_t* bin_count, int32_t* bin_off, int nbins,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(bin_offsets_kernel, dim3(1), dim3(256), 0, s, stripes, bin_count, bin_off, nbins);
     return hipGetLastError();
 }
 hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,

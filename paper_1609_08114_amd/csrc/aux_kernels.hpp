@@ -23,9 +23,17 @@ struct VariantTable {
 };
 
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);
-hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* bin_count,
+// classify adds its blocks' bin histograms into kBinStripes copies of the
+// bin counters (stripes[bin * kBinStripes + stripe], zeroed beforehand);
+// bin_offsets sums the copies into bin_count and writes the exclusive prefix
+// to bin_off.
+constexpr int kClassifyMaxBlocks = 2048;
+constexpr int kBinStripes = 64;
+int classify_blocks(int64_t count);
+hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* stripes,
                            hipStream_t s);
-hipError_t launch_bin_offsets(const int32_t* bin_count, int32_t* bin_off, int nbins, hipStream_t s);
+hipError_t launch_bin_offsets(const int32_t* stripes, int32_t* bin_count, int32_t* bin_off, int nbins,
+                              hipStream_t s);
 hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
                           int32_t* list, hipStream_t s);
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s);

@@ -73,7 +73,7 @@ struct blp_handle_s {
     int gm_occ = 1;
     // device buffers
     DevBuf meta;     // m, n, kind (int32) + a_off, row_off, col_off (int64) for non-uniform batches
-    DevBuf counters; // bin_count, bin_fill, bin_head, bin_off (4 x nbins int32)
+    DevBuf counters; // bin_count, bin_fill, bin_head, bin_off (4 x nbins int32), striped bin counters
     DevBuf binid, list;
     DevBuf ws;       // streaming-kernel workspace
     DevBuf own_status, own_iters, own_obj, own_x, own_y;
@@ -438,7 +438,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.timers = h->timers;
 #endif
     const int nreg = h->nreg, nbins = nreg + 2;
-    HIP_TRY(h, h->counters.reserve(sizeof(int32_t) * 4 * nbins));
+    // bin_count, bin_fill, bin_head, bin_off, then the striped bin counters
+    HIP_TRY(h, h->counters.reserve(sizeof(int32_t) * (4 + (size_t)kBinStripes) * nbins));
     int32_t* bin_count = h->counters.as<int32_t>();
     P.bin_len = bin_count;
     P.bin_head = bin_count + 2 * nbins;
@@ -524,9 +525,11 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     int32_t* bin_count = h->counters.as<int32_t>();
     int32_t* bin_fill = bin_count + nbins;
     HIP_TRY(h, h->mark(nbins, true, s));
-    HIP_TRY(h, launch_reset(bin_count, 3 * nbins, s));
-    HIP_TRY(h, launch_classify(sp.P, variant_table(h), h->binid.as<int32_t>(), bin_count, s));
-    HIP_TRY(h, launch_bin_offsets(bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
+    // zero the counters and the striped bin counters (bin_off is rewritten)
+    int32_t* stripes = bin_count + 4 * nbins;
+    HIP_TRY(h, launch_reset(bin_count, (4 + kBinStripes) * nbins, s));
+    HIP_TRY(h, launch_classify(sp.P, variant_table(h), h->binid.as<int32_t>(), stripes, s));
+    HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
     HIP_TRY(h, launch_scatter(sp.P.count, nbins, h->binid.as<int32_t>(), sp.P.bin_off, bin_fill,
                               h->list.as<int32_t>(), s));
     HIP_TRY(h, h->mark(nbins, false, s));
