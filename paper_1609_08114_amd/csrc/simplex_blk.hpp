@@ -278,8 +278,24 @@ simplex_blk_kernel(KParams P) {
             lds_barrier();
             continue;
         }
-        int bad = prep_rows<NT>(P, Lin, t, s_sig, s_b, s_flag);
-        for (int j = t; j < n; j += NT) s_c[j] = P.c[L.col_off + j];
+        // every load of the LP is issued before any is used, so the rows',
+        // costs' and the tile's loads share one memory round trip
+        constexpr int RPT = (RP + NT - 1) / NT, CPT = (CP + NT - 1) / NT;
+        double lb[RPT], lc[CPT];
+        int ls[RPT];
+        // (unconditional loads, indices clamped into the LP: m, n >= 1 here;
+        // a select on a loaded value would wait for it at once)
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int i = min(t + u * NT, m - 1);
+            lb[u] = P.b[Lin.row_off + i];
+            ls[u] = P.sense[Lin.row_off + i];
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) lc[u] = P.c[L.col_off + min(t + u * NT, n - 1)];
+        // keep these loads ahead of the tile's: loads complete in issue order,
+        // so the rows can be prepared while the tile is still arriving
+        __builtin_amdgcn_sched_barrier(0);
         // A straight into the tile (scaled below, once the row signs are known)
         // with range-checked buffer loads: the resource covers this LP's m x n
         // block, so rows >= m read as 0; columns >= n get an offset beyond it.
@@ -296,6 +312,20 @@ simplex_blk_kernel(KParams P) {
                 for (int r = 0; r < RB; ++r)
                     T[r][c] = __builtin_bit_cast(
                         double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(cofs + (unsigned)(r * n) * 8u), 0, 0));
+            }
+        }
+        int bad = 0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int i = t + u * NT;
+            if (i < m) bad |= prep_row(i, lb[u], ls[u], s_sig, s_b, s_flag);
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = t + u * NT;
+            if (j < n) {
+                s_c[j] = lc[u];
+                bad |= !isfinite(lc[u]);
             }
         }
         lds_barrier();

@@ -31,21 +31,22 @@ namespace blp {
 // for ">=" rows (Sec. 3, Eq. (2)); a negative "<=" rhs makes the initial
 // basic solution infeasible, so that row is negated back and gets a surplus
 // and an artificial variable (the two-phase method of Sec. 3).
+__device__ __forceinline__ int prep_row(int i, double bi, int sense, double* s_sig, double* s_b,
+                                        unsigned char* s_flag) {
+    const int ge = sense != 0;
+    const double ble = ge ? -bi : bi;
+    const int art = ble < 0.0;
+    const double sg = art ? (ge ? 1.0 : -1.0) : (ge ? -1.0 : 1.0);
+    s_sig[i] = sg;
+    s_b[i] = sg * bi;
+    s_flag[i] = (unsigned char)((ge ? RF_GE : 0) | (art ? RF_ART : 0));
+    return !isfinite(bi);
+}
 template <int NT>
 __device__ __forceinline__ int prep_rows(const KParams& P, const LpRef& L, int t, double* s_sig, double* s_b,
                                          unsigned char* s_flag) {
     int bad = 0;
-    for (int i = t; i < L.m; i += NT) {
-        const double bi = P.b[L.row_off + i];
-        const int ge = P.sense[L.row_off + i] != 0;
-        const double ble = ge ? -bi : bi;
-        const int art = ble < 0.0;
-        const double sg = art ? (ge ? 1.0 : -1.0) : (ge ? -1.0 : 1.0);
-        s_sig[i] = sg;
-        s_b[i] = sg * bi;
-        s_flag[i] = (unsigned char)((ge ? RF_GE : 0) | (art ? RF_ART : 0));
-        bad |= !isfinite(bi);
-    }
+    for (int i = t; i < L.m; i += NT) bad |= prep_row(i, P.b[L.row_off + i], P.sense[L.row_off + i], s_sig, s_b, s_flag);
     for (int j = t; j < L.n; j += NT) bad |= !isfinite(P.c[L.col_off + j]);
     return bad;
 }
