@@ -192,7 +192,7 @@ simplex_blk_kernel(KParams P) {
     // reads its mirror entries without a bounds branch
     __shared__ double s_f[2][RS * 64], s_p[2][CS * 64];
     __shared__ double s_sig[RP], s_b[RP], s_c[CP], s_w[CP];
-    __shared__ int s_colvar[CP], s_basis[RP], s_artrow[RP], s_rank[RP];
+    __shared__ int s_artrow[RP], s_rank[RP];
     __shared__ unsigned char s_flag[RP];
     __shared__ int s_k, s_nart, s_bad;
     // shared-constraint mode: objective coefficients of the basis, per row
@@ -423,33 +423,53 @@ simplex_blk_kernel(KParams P) {
         const int id_lim = n + m;
         int iters = 0, degen = 0, st = -1;
 
-        // outputs of LP k from the mirrors
+        // Outputs of LP k straight from the mirrors (wave 0; the mirrors are
+        // identical in every wave).  Every structural and logical variable
+        // sits in exactly one place, a row (basic: x = rhs, dual 0) or a
+        // slot (nonbasic: x = 0, dual from the objective row), so x and y are
+        // written by one scatter each, without LDS or barriers; the duals
+        // take the same signs as the oracle's (-d for "<=" rows, also on a
+        // zero d).  Only s_flag is read, which no other wave writes before
+        // the next pop's barrier.
         auto extract = [&]() __attribute__((always_inline)) {
             BLP_T(t_x0);
-            lds_barrier();
             if (t < 64) {
+                const double z = -mirror_at(bR, ROW_OBJ);
+                const int sto = st == ST_OPTIMAL && !isfinite(z) ? ST_NUMERICAL : st;
+                const bool nan_out = sto == ST_NUMERICAL;
+                const double qnan = __builtin_nan("");
 #pragma unroll
                 for (int q = 0; q < CS; ++q) {
-                    const int j = q * 64 + lane;
-                    if (j < CP) {
-                        s_p[1][j] = dO[q];
-                        s_colvar[j] = cv[q];
+                    const int j = q * 64 + lane, v = cv[q];
+                    if (j < COL_RHS) {
+                        if (v < n) {
+                            P.x[L.col_off + v] = nan_out ? qnan : 0.0;
+                        } else if (v < n + m) {
+                            const double d = dO[q];
+                            P.y[L.row_off + (v - n)] = nan_out ? qnan : ((s_flag[v - n] & RF_GE) ? d : -d);
+                        }
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < RS; ++q) {
-                    const int i = q * 64 + lane;
-                    if (i < RP) s_f[1][i] = bR[q];
+                    const int i = q * 64 + lane, v = bs[q];
                     if (i < m) {
-                        s_basis[i] = bs[q];
-                        if ((dead >> q) & 1u) s_flag[i] |= RF_DEAD;
+                        if (v < n) {
+                            P.x[L.col_off + v] = nan_out ? qnan : bR[q];
+                        } else if (v < n + m) {
+                            P.y[L.row_off + (v - n)] = nan_out ? qnan : ((s_flag[v - n] & RF_GE) ? 0.0 : -0.0);
+                        }
                     }
                 }
+                if (lane == 0) {
+                    P.status[k] = sto;
+                    P.iters[k] = iters;
+                    P.obj[k] = (sto == ST_OPTIMAL || sto == ST_ITER_LIMIT) ? z
+                               : sto == ST_UNBOUNDED                      ? __builtin_inf()
+                               : sto == ST_INFEASIBLE                     ? -__builtin_inf()
+                                                                          : qnan;
+                }
             }
-            lds_barrier();
-            write_outputs<NT>(P, L, k, t, st, iters, ROW_OBJ, COL_RHS, s_p[1], s_f[1], s_colvar, s_basis, s_flag, s_p[0],
-                              s_f[0]);
-            lds_barrier();
             BLP_T(t_x1);
             BLP_TACC(TM_EXTRACT, t_x0, t_x1);
             BLP_TCOUNT(TM_PIVOTS, (unsigned long long)iters);
