@@ -252,26 +252,41 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             // In phase 2 a slot holding an artificial variable never enters
             // again and feeds no output (pricing skips it, duals come from
             // the logical columns), so its column is not streamed.
+            // A wave streams U columns per step (j0 + u NW), all their loads
+            // issued before any is used: with one column per step each wave
+            // had QM loads in flight and the update was bound by memory
+            // latency, not bandwidth.
             const bool skip_art = mode == 2;
-            for (int j = wave; j < C; j += NW) {
-                if (skip_art && S.colvar[j] >= id_lim && j != RHS) continue;
-                const double pj = S.p[j];
-                const bool je = j == e;
-                double v[QM];
+            constexpr int U = QM >= 8 ? 1 : 8 / QM;
+            for (int j0 = wave; j0 < C; j0 += NW * U) {
+                bool live[U];
+                double v[U][QM];
 #pragma unroll
-                for (int q = 0; q < QM; ++q) {
-                    const int i = lane + 64 * q;
-                    v[q] = (i < ldk && !je) ? Tg[at(i, j)] : 0.0;
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * NW;
+                    live[u] = j < C && !(skip_art && S.colvar[j] >= id_lim && j != RHS);
+                    const bool je = j == e;
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) {
+                        const int i = lane + 64 * q;
+                        v[u][q] = (live[u] && i < ldk && !je) ? Tg[at(i, j)] : 0.0;
+                    }
                 }
 #pragma unroll
-                for (int q = 0; q < QM; ++q) {
-                    const int i = lane + 64 * q;
-                    if (i < ldk) {
-                        double w = __builtin_fma(nf[q], pj, v[q]);
-                        w = i == l ? pj : w;
-                        Tg[at(i, j)] = w;
-                        if (i == act) S.d[j] = w;
-                        if (j == RHS) S.b[i] = w;
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * NW;
+                    if (!live[u]) continue;
+                    const double pj = S.p[j];
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) {
+                        const int i = lane + 64 * q;
+                        if (i < ldk) {
+                            double w = __builtin_fma(nf[q], pj, v[u][q]);
+                            w = i == l ? pj : w;
+                            Tg[at(i, j)] = w;
+                            if (i == act) S.d[j] = w;
+                            if (j == RHS) S.b[i] = w;
+                        }
                     }
                 }
             }
