@@ -431,6 +431,25 @@ def bench_classes(blp, torch, lpgen) -> dict:
             byt = n_batch * (24.0 * n + 8.0 * n + 16.0)
             entry.update({"kernel_ms": round(kb, 4), "hbm_bytes": byt, "hbm_GBps": round(byt / kb / 1e6, 1),
                           "hbm_frac": round(byt / kb / 1e6 / PEAK_HBM_GBS, 4)})
+        if name == "type2_200x200":
+            # the streaming kernel rewrites the condensed tableau every pivot:
+            # 16 B per cell of ldk rows x (n + n_art + 1) columns in phase 1,
+            # fewer in phase 2 (artificial columns skipped), so this is an
+            # upper bound; the algorithmic figure is the full tableau of
+            # Sec. 3.1 ((m + 2) x (n + m + n_art + 1)) at every pivot
+            m, n = int(hb.m[0]), int(hb.n[0])
+            sense = hb.sense.reshape(n_batch, m) != 0
+            b = hb.b.reshape(n_batch, m)
+            nart = ((np.where(sense, -b, b)) < 0).sum(axis=1)
+            it = out["iters"][:n_batch].cpu().numpy().astype(np.float64)
+            ldk = ((m + 2 + 15) // 16) * 16
+            gms = float(kms[len(blp.variants())])
+            upper = float((it * 16.0 * ldk * (n + nart + 1)).sum())
+            alg = float((it * 16.0 * (m + 2) * (n + m + nart + 1)).sum())
+            entry.update({"streaming_kernel_ms": round(gms, 3), "pivots_per_lp": round(float(it.mean()), 1),
+                          "streamed_GBps_upper": round(upper / gms / 1e6, 1),
+                          "streamed_hbm_frac_upper": round(upper / gms / 1e6 / PEAK_HBM_GBS, 4),
+                          "algorithmic_full_tableau_GBps": round(alg / gms / 1e6, 1)})
         if n_single:
             sub = lpgen.config(cfg, range(n_single), part=part) if part else lpgen.config(cfg, range(n_single))
             sdb = blp.DeviceBatch.from_host(sub)
