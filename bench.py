@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+PEAK_LDS_GBS = 78643.2    # 256 CUs x 128 B/clk x 2.4 GHz
 METRIC = "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr\u22641e-9"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel__type1_m100_n100_K50000.json")
 KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_blk.hpp",
@@ -150,6 +151,12 @@ def main():
                 "algorithmic_flops": flops, "executed_flops": executed,
                 "executed_frac": round(executed / (dom_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
                 "pivots": int(iters.sum()),
+                # the same update priced as a tableau resident in LDS (read and
+                # write 8 bytes per full-tableau entry per pivot): the bound an
+                # LDS-staged kernel could not exceed; this kernel keeps the
+                # tableau in registers instead
+                "lds_model_GBps": round(flops * 8.0 / (dom_ms / 1e3) / 1e9, 1),
+                "lds_model_frac": round(flops * 8.0 / (dom_ms / 1e3) / 1e9 / PEAK_LDS_GBS, 4),
                 "hbm_input_bytes": input_bytes,
                 "hbm_frac_of_input_read": round(input_bytes / (dom_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 

@@ -185,26 +185,30 @@ __global__ void hyperbox_kernel(KParams P) {
 }
 
 // Eq. (7) for a uniform batch of n-variable boxes laid out back to back:
-// one wave per group of 64 LPs.  c, l, u are read with consecutive lanes on
+// one wave per group of G LPs (64; 32 for n > 16).  c, l, u are read with consecutive lanes on
 // consecutive doubles and x is written the same way; c and h go through LDS
 // (rows padded to n + 1 doubles against bank conflicts) so that lane i can
 // sum LP i's products in increasing order, as the per-LP kernel does.
 // Invalid-data flags are OR-ed per LP in LDS.
+template <int G>
 __global__ void __launch_bounds__(64) hyperbox_tile_kernel(KParams P) {
     extern __shared__ double s_mem[];
     const int N = P.un, NP = N + 1;
     double* s_c = s_mem;
-    double* s_h = s_mem + 64 * NP;
-    int* s_fl = reinterpret_cast<int*>(s_h + 64 * NP);
+    double* s_h = s_mem + G * NP;
+    int* s_fl = reinterpret_cast<int*>(s_h + G * NP);
     const int lane = threadIdx.x;
     const int64_t K = P.count;
+    // e / N as a multiply-high: exact for e < 64 * 48 (the fraction of e / N
+    // stays below 1 - 1/N, the rounding error below e / 2^32)
+    const unsigned magic = (unsigned)((0x100000000ull + N - 1) / N);
     constexpr int UNR = 8;
-    for (int64_t g = blockIdx.x; g * 64 < K; g += gridDim.x) {
-        const int64_t k0 = g * 64;
-        const int nl = (int)(K - k0 < 64 ? K - k0 : 64);
+    for (int64_t g = blockIdx.x; g * G < K; g += gridDim.x) {
+        const int64_t k0 = g * G;
+        const int nl = (int)(K - k0 < G ? K - k0 : G);
         const int64_t e0 = k0 * N;
         const int ne = nl * N;
-        s_fl[lane] = 0;
+        if (lane < G) s_fl[lane] = 0;
         __syncthreads();
         for (int eb = 0; eb < ne; eb += 64 * UNR) {
             double cv[UNR], lv[UNR], uv[UNR];
@@ -222,7 +226,7 @@ __global__ void __launch_bounds__(64) hyperbox_tile_kernel(KParams P) {
                 if (e < ne) {
                     const double h = cv[q] < 0.0 ? lv[q] : uv[q];
                     P.x[e0 + e] = h;
-                    const int lk = e / N, i = e - lk * N;
+                    const int lk = (int)__umulhi((unsigned)e, magic), i = e - lk * N;
                     s_c[lk * NP + i] = cv[q];
                     s_h[lk * NP + i] = h;
                     const int f = ((!isfinite(cv[q]) || !isfinite(lv[q]) || !isfinite(uv[q])) ? 1 : 0) |
@@ -348,8 +352,15 @@ static unsigned grid_for(int64_t items, int per_block, int64_t cap) {
 }
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s) {
     if (P.uniform && !P.list && P.un >= 1 && P.un <= kBoxTileMaxN) {
-        const size_t lds = sizeof(double) * 2 * 64 * (size_t)(P.un + 1) + sizeof(int) * 64;
-        hipLaunchKernelGGL(hyperbox_tile_kernel, dim3(grid_for(P.count, 64, 1 << 15)), dim3(64), lds, s, P);
+        // groups of 64 LPs per wave; 32 for larger n, so that twice as many
+        // waves fit the LDS of a CU and keep loads in flight
+        if (P.un <= 16) {
+            const size_t lds = sizeof(double) * 2 * 64 * (size_t)(P.un + 1) + sizeof(int) * 64;
+            hipLaunchKernelGGL(hyperbox_tile_kernel<64>, dim3(grid_for(P.count, 64, 1 << 15)), dim3(64), lds, s, P);
+        } else {
+            const size_t lds = sizeof(double) * 2 * 32 * (size_t)(P.un + 1) + sizeof(int) * 32;
+            hipLaunchKernelGGL(hyperbox_tile_kernel<32>, dim3(grid_for(P.count, 32, 1 << 15)), dim3(64), lds, s, P);
+        }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P);
