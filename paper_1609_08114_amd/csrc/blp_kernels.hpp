@@ -138,6 +138,17 @@ __device__ __forceinline__ int64_t work_len(const KParams& P) {
 __device__ __forceinline__ int64_t work_item(const KParams& P, int64_t q) {
     return P.list ? (int64_t)P.list[P.bin_off[P.bin] + q] : q;
 }
+// Next queue position of this launch's work list (one lane calls it).  On a
+// workgroup's first pop the head is read plainly first: when the list is
+// empty (or already exhausted) the workgroups of the launch leave without an
+// atomic each, which thousands of them would serialise on one address.
+// Later pops go straight to the atomic (the extra read would add a memory
+// round trip per LP).
+__device__ __forceinline__ int pop_position(const KParams& P, int64_t len, bool first) {
+    int* head = P.bin_head + P.bin;
+    if (first && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) return (int)len;
+    return atomicAdd(head, 1);
+}
 
 // ---------------------------------------------------------------------------
 // Wave-wide arg-max of (key, id) pairs under the total order

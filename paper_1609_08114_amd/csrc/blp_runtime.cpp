@@ -96,6 +96,25 @@ struct blp_handle_s {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_sig;
     hipStream_t cap_stream = nullptr;
+    // persistent kernel classes of a mixed batch run concurrently: forked
+    // from the solve stream onto these (default priority) and joined back
+    static constexpr int kForks = 3;
+    hipStream_t fork[kForks] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[kForks] = {nullptr, nullptr, nullptr};
+    hipError_t ensure_forks() {
+        for (int i = 0; i < kForks; ++i) {
+            if (!fork[i]) {
+                hipError_t e = hipStreamCreateWithFlags(&fork[i], hipStreamNonBlocking);
+                if (e != hipSuccess) return e;
+            }
+            if (!join_ev[i]) {
+                hipError_t e = hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (!fork_ev) return hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
+        return hipSuccess;
+    }
     DevBuf tune;  // autotuner scratch (sample list + counters)
     DevBuf shared_ctr;  // queue head of blp_solve_shared
     // host-resident pipeline: two child handles (own buffers), two streams,
@@ -264,6 +283,11 @@ void blp_destroy(blp_handle h) {
     for (auto e : h->ev1) (void)hipEventDestroy(e);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (int i = 0; i < blp_handle_s::kForks; ++i) {
+        if (h->fork[i]) (void)hipStreamDestroy(h->fork[i]);
+        if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     delete h;
 }
 
@@ -536,28 +560,48 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     return BLP_SUCCESS;
 }
 
-// One persistent launch per kernel class that can receive LPs.
+// One persistent launch per kernel class that can receive LPs.  For a mixed
+// batch (not uniform, at least kForkMinLps LPs) the launches are forked onto
+// internal streams (each waits for the binning on s) and joined back into s:
+// the bins of a mixed batch are small, each kernel's duration is set by its
+// slowest LP, and run one after another they leave most of the GPU idle.  A
+// uniform batch has one dominant class, and there the fork and join would
+// only add their own latency.
+static constexpr int64_t kForkMinLps = 2048;
 static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s) {
     const int nreg = h->nreg;
     const int64_t K = sp.P.count;
     KParams P = sp.P;
     P.direct = 0;
-    for (int v = 0; v < nreg; ++v) {
-        if (!sp.maybe[v]) continue;
+    std::vector<int> cls;  // 0..nreg-1 register variants, nreg streaming
+    for (int v = 0; v < nreg; ++v)
+        if (sp.maybe[v]) cls.push_back(v);
+    if (sp.any_simplex) cls.push_back(nreg);
+    const int nc = (int)cls.size();
+    const bool forked = nc > 1 && !sp.uni && K >= kForkMinLps;
+    const int nf = forked ? std::min(nc - 1, (int)blp_handle_s::kForks) : 0;
+    if (forked) {
+        HIP_TRY(h, h->ensure_forks());
+        HIP_TRY(h, hipEventRecord(h->fork_ev, s));
+        for (int i = 0; i < nf; ++i) HIP_TRY(h, hipStreamWaitEvent(h->fork[i], h->fork_ev, 0));
+    }
+    for (int i = 0; i < nc; ++i) {
+        const int v = cls[i];
+        // the last class (the streaming kernel when present) stays on s
+        hipStream_t st = (forked && i < nc - 1) ? h->fork[i % nf] : s;
         KParams Q = P;
         Q.bin = v;
-        const int grid = (int)std::min<int64_t>(h->reg_workers[v], K);
-        HIP_TRY(h, h->mark(v, true, s));
-        HIP_TRY(h, h->variants[v].launch(Q, grid, s));
-        HIP_TRY(h, h->mark(v, false, s));
+        HIP_TRY(h, h->mark(v, true, st));
+        if (v < nreg) {
+            HIP_TRY(h, h->variants[v].launch(Q, (int)std::min<int64_t>(h->reg_workers[v], K), st));
+        } else {
+            HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st));
+        }
+        HIP_TRY(h, h->mark(v, false, st));
     }
-    if (sp.any_simplex) {
-        KParams Q = P;
-        Q.bin = nreg;
-        const int grid = (int)std::min<int64_t>(sp.gm_workers, K);
-        HIP_TRY(h, h->mark(nreg, true, s));
-        HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s));
-        HIP_TRY(h, h->mark(nreg, false, s));
+    for (int i = 0; i < nf; ++i) {
+        HIP_TRY(h, hipEventRecord(h->join_ev[i], h->fork[i]));
+        HIP_TRY(h, hipStreamWaitEvent(s, h->join_ev[i], 0));
     }
     return BLP_SUCCESS;
 }

@@ -233,7 +233,7 @@ simplex_blk_kernel(KParams P) {
                 s_pending = -1;
             } else if (!SH && !P.direct) {
                 if (first) {
-                    const int q = atomicAdd(P.bin_head + P.bin, 1);
+                    const int q = pop_position(P, len, true);
                     kk = q < len ? (int)work_item(P, q) : -1;
                 } else {
                     kk = pf_k != -2 ? pf_k : (pf_q < len ? (int)work_item(P, pf_q) : -1);

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             if (P.direct)
                 q = first ? P.direct_first + (int64_t)blockIdx.x : len;
             else
-                q = atomicAdd(P.bin_head + P.bin, 1);
+                q = pop_position(P, len, first);
             s_k = q < len ? (int)work_item(P, q) : -1;
             s_bad = 0;
         }

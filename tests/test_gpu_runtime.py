@@ -198,3 +198,31 @@ def test_row_major_workspace_identical():
         assert np.array_equal(a[k], b[k])
     for k in ("obj", "x", "y"):
         assert np.array_equal(_bits(a[k]), _bits(b[k])), k
+
+
+def test_mixed_batch_classes_run_concurrently():
+    # A mixed batch of at least 2,048 LPs runs its kernel classes on forked
+    # streams: every LP as the oracle solves it (all of them, m = n in
+    # 20..150 over several register variants), and graph replays of the same
+    # forked launch sequence identical to the eager solve.
+    import torch
+
+    import oracle
+    import paper_1609_08114_amd as blp
+    from solve_util import compare
+    hb = lpgen.config(5, range(2600), part="simplex")
+    g = gpu_solve(hb)
+    assert sum(1 for c in g["bins"][:-2] if c > 0) >= 3  # several classes at once
+    compare(hb, g, oracle.solve_batch(hb), strict=True, tag="forked")
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver(graph=True)
+    try:
+        for rep in range(3):
+            out = s.solve(db)
+            torch.cuda.synchronize()
+            _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+            assert np.array_equal(out["status"][:hb.count].cpu().numpy(), g["status"])
+            assert np.array_equal(_bits(out["obj"][:hb.count].cpu().numpy()), _bits(g["obj"]))
+            assert np.array_equal(_bits(out["x"][:hb.c.size].cpu().numpy()), _bits(g["x"][:hb.c.size]))
+    finally:
+        s.close()
