@@ -4,7 +4,9 @@
 //    waves per SIMD)
 // giving a maximum tableau of 64*waves/TC rows by TC*CT columns (objective
 // rows and the rhs column included).  The scheduler sends each LP
-// to the fitting variant of smallest area.
+// to the fitting variant of smallest area, the first in this order among
+// equal areas: the row-tile w4/w8 variants (the first design, kept for
+// comparison and the autotuner) come after the block tiles of their shapes.
 #pragma once
 
 #include "blp_kernels.hpp"
@@ -29,9 +31,11 @@ const RegVariant* reg_variants(int* count);
     BLP_REG_VARIANT("w1_r16_c16",    1, 4,   4, 4)           \
     BLP_REG_VARIANT("w1_r32_c32",    1, 2,  16, 2)           \
     BLP_REG_VARIANT("w2_r64_c64",    2, 2,  32, 1)           \
-    BLP_REG_VARIANT("w4_r128_c112",  4, 2,  56, 2)           \
     BLP_BLK_VARIANT("b4_r112_c112",  4, 16, 7, 7, 2)         \
+    BLP_BLK_VARIANT("b8_r128_c112",  8, 16, 4, 7, 2)         \
+    BLP_BLK_VARIANT("b8_r128_c128",  8, 16, 4, 8, 2)         \
     BLP_BLK_VARIANT("b8_r160_c160",  8, 16, 5, 10, 2)        \
+    BLP_REG_VARIANT("w4_r128_c112",  4, 2,  56, 2)           \
     BLP_REG_VARIANT("w8_r128_c128",  8, 4,  32, 2)
 // clang-format on
 
