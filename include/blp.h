@@ -198,7 +198,9 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_o
  * optima, x and y may therefore differ from independent solves; statuses and
  * optima do not.  Needs m + 2 <= 112 and
  * n + n_art + 1 <= 112 (n_art = rows whose "<=" form has a negative rhs),
- * else BLP_ERR_TOO_LARGE.  Reads b, sense and the first 65 objectives back
+ * else BLP_ERR_TOO_LARGE.  A handle whose options force a register-tile
+ * variant (variant >= 0) runs the cold solves with that variant, and fails
+ * with BLP_ERR_TOO_LARGE if it cannot hold them.  Reads b, sense and the first 65 objectives back
  * to the host once (synchronising the stream); the solve itself is ordered
  * on the stream.
  * The handle keeps no results of this call (blp_backward and

@@ -129,6 +129,15 @@ __device__ __forceinline__ LpRef lp_ref(const KParams& P, int64_t k) {
     return r;
 }
 
+// Where LP k reads its constraints: its own A, b and sense, or, in a launch
+// over one shared constraint set, offset 0 for every LP (the objective and
+// the outputs stay per LP).
+__device__ __forceinline__ LpRef lp_in(const KParams& P, const LpRef& L) {
+    LpRef r = L;
+    if (P.shared_in) r.a_off = r.row_off = 0;
+    return r;
+}
+
 __device__ __forceinline__ int lp_kind(const KParams& P, int64_t k) { return P.uniform ? P.ukind : P.kind[k]; }
 
 // Entry count of this launch's work list.

@@ -832,9 +832,16 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     P.bin = 0;
     if (!warm) {
         // unrelated directions: every objective is a cold solve, by the
-        // register kernel of the same tile, reading the one constraint set
+        // first register kernel of the same tile (or the forced variant),
+        // every LP reading the one constraint set
         int v = -1;
-        for (int i = 0; i < h->nreg; ++i)
+        if (h->opt.variant >= 0) {
+            v = h->opt.variant;
+            if (h->variants[v].max_rows < m + 2 || h->variants[v].max_cols < n + nart + 1)
+                return fail(h, BLP_ERR_TOO_LARGE, "variant %s cannot hold the shared constraints",
+                            h->variants[v].name);
+        }
+        for (int i = 0; i < h->nreg && v < 0; ++i)
             if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols) v = i;
         if (v < 0) return fail(h, BLP_ERR_STATE, "no register variant of the shared tile shape");
         P.shared_in = 1;

@@ -270,8 +270,8 @@ simplex_blk_kernel(KParams P) {
 
         // ------------------------------------------------------------ load
         LpRef L = lp_ref(P, k);
-        LpRef Lin = L;  // where the constraint data are read
-        if (SH || P.shared_in) Lin.a_off = Lin.row_off = 0;
+        LpRef Lin = lp_in(P, L);  // where the constraint data are read
+        if (SH) Lin.a_off = Lin.row_off = 0;
         const int m = L.m, n = L.n;
         if (m > RP - 2 || n + 1 > CP) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);

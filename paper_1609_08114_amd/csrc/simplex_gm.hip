@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
 
         // ------------------------------------------------------------ load
         const LpRef L = lp_ref(P, k);
+        const LpRef Lin = lp_in(P, L);  // constraint reads
         const int m = L.m, n = L.n;
         if (m > ld - 2 || n + 1 > cg_max) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             S.b[i] = 0.0;
         }
         __syncthreads();
-        int bad = prep_rows<NT>(P, L, t, S.sig, S.b, S.flag);
+        int bad = prep_rows<NT>(P, Lin, t, S.sig, S.b, S.flag);
         __syncthreads();
         if (t < 64) scan_art_rows(m, lane, S.flag, S.artrow, S.rank, &s_nart);
         __syncthreads();
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
         for (int i = wave; i < m; i += NW) {
             const double sg = S.sig[i];
             for (int j = lane; j < n; j += 64) {
-                const double a = P.A[L.a_off + (int64_t)i * n + j];
+                const double a = P.A[Lin.a_off + (int64_t)i * n + j];
                 bad |= !isfinite(a);
                 Tg[at(i, j)] = sg * a;
             }
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                     if (j < n) {
                         for (int q = 0; q < nart; ++q) {
                             const int ii = S.artrow[q];
-                            acc = acc + S.sig[ii] * P.A[L.a_off + (int64_t)ii * n + j];
+                            acc = acc + S.sig[ii] * P.A[Lin.a_off + (int64_t)ii * n + j];
                         }
                     } else if (j < RHS) {
                         acc = -1.0;

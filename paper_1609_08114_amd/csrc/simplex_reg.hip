@@ -89,6 +89,7 @@ simplex_reg_kernel(KParams P) {
 
         // ------------------------------------------------------------ load
         const LpRef L = lp_ref(P, k);
+        const LpRef Lin = lp_in(P, L);  // constraint reads
         const int m = L.m, n = L.n;
         if (m > RP - 2 || n + 1 > CP) {  // never routed here; no LDS write past the arrays
             write_numerical<NT>(P, L, k, t, ST_INTERNAL);
@@ -100,7 +101,7 @@ simplex_reg_kernel(KParams P) {
             s_b[i] = 0.0;
         }
         __syncthreads();
-        int bad = prep_rows<NT>(P, L, t, s_sig, s_b, s_flag);
+        int bad = prep_rows<NT>(P, Lin, t, s_sig, s_b, s_flag);
         for (int j = t; j < n; j += NT) s_d[j] = P.c[L.col_off + j];  // objective row source
         __syncthreads();
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
@@ -119,7 +120,7 @@ simplex_reg_kernel(KParams P) {
                 if (j < n) {
                     for (int q = 0; q < nart; ++q) {
                         const int ii = s_artrow[q];
-                        acc = acc + s_sig[ii] * P.A[L.a_off + (int64_t)ii * n + j];
+                        acc = acc + s_sig[ii] * P.A[Lin.a_off + (int64_t)ii * n + j];
                     }
                 } else if (j < n + nart) {
                     acc = -1.0;
@@ -142,7 +143,7 @@ simplex_reg_kernel(KParams P) {
                 const int e = t + q * NT;
                 const int i = r0 + e / CP, j = e % CP;
                 const bool ld = e < SR * CP && i < m && j < n;
-                av[q] = ld ? P.A[L.a_off + (int64_t)i * n + j] : 0.0;
+                av[q] = ld ? P.A[Lin.a_off + (int64_t)i * n + j] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {

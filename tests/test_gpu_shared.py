@@ -13,12 +13,12 @@ from solve_util import REL, crafted_batch
 pytestmark = pytest.mark.gpu
 
 
-def _shared_gpu(A, b, sense, C):
+def _shared_gpu(A, b, sense, C, variant=-1):
     import torch
 
     import paper_1609_08114_amd as blp
     dev = torch.device("cuda")
-    s = blp.Solver()
+    s = blp.Solver(variant=variant)
     try:
         out = s.solve_shared(torch.from_numpy(np.ascontiguousarray(A, np.float64).ravel()).to(dev),
                              torch.from_numpy(np.ascontiguousarray(b, np.float64)).to(dev),
@@ -38,8 +38,8 @@ def _oracle(A, b, sense, C):
     return oracle.solve_batch(crafted_batch(lps))
 
 
-def _check(A, b, sense, C, tag):
-    g = _shared_gpu(A, b, sense, C)
+def _check(A, b, sense, C, tag, variant=-1):
+    g = _shared_gpu(A, b, sense, C, variant)
     o = _oracle(A, b, sense, C)
     K, n = C.shape
     m = len(b)
@@ -164,6 +164,25 @@ def test_infeasible_constraints():
     Cs = np.stack([1.0 + 0.1 * t, 1.0 - 0.1 * t], axis=1)  # close directions: the warm-start kernel
     g, o, _ = _check(A, b, sense, Cs, "infeasible-sweep")
     assert (g["status"] == oracle.INFEASIBLE).all()
+
+
+def test_cold_route_on_every_register_variant():
+    # unrelated directions take the cold route; forcing each register-tile
+    # variant in turn checks that every kernel reads the one shared
+    # constraint set (A, b, sense at offset 0) and not per-LP offsets
+    import paper_1609_08114_amd as blp
+    rng = np.random.default_rng(13)
+    m, n = 5, 5
+    A = rng.uniform(0.5, 2.0, size=(m, n))
+    b = rng.uniform(5.0, 10.0, size=m)
+    sense = np.zeros(m, np.int8)
+    sense[2] = 1  # one ">=" row: phase 1 with one artificial
+    b[2] = 1.0
+    C = rng.normal(size=(300, n))
+    for v, (name, _, _) in enumerate(blp.variants()):
+        print(f"[shared-cold] variant {name}", flush=True)
+        g, o, _ = _check(A, b, sense, C, f"cold-{name}", variant=v)
+        assert (o["status"] == oracle.OPTIMAL).any()
 
 
 def test_shared_errors():
