@@ -186,6 +186,11 @@ def main():
     if not args.no_classes:
         shared = bench_shared(blp, torch, lpgen, oracle_check=not args.no_cpu)
 
+    # -------------------- pivot rules: RPC (Sec. 4.2) against LPC, same batch
+    rules = None
+    if not args.no_classes:
+        rules = pivot_rules(blp, torch, db, K, obj, iters, value)
+
     # ------------------------------------------- layout ablation (Sec. 4.3)
     ablation = None
     if not args.no_classes:
@@ -239,6 +244,7 @@ def main():
         "per_class": per_class,
         "layout_ablation": ablation,
         "shared_constraints": shared,
+        "pivot_rules": rules,
     }
     print(json.dumps(line), flush=True)
 
@@ -390,6 +396,25 @@ def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:
         res[name] = entry
         log(f"shared {name}: {entry}")
     return res
+
+
+def pivot_rules(blp, torch, db, K, obj_lpc, iters_lpc, rate_lpc, seed=12345) -> dict:
+    """The random-positive-coefficient rule (Sec. 4.2) on the same resident
+    batch as the headline LPC run: LPs/s, pivots per LP and agreement of the
+    optima (both rules reach the same optimum; the pivot paths differ)."""
+    log("pivot rules: RPC on the headline batch")
+    ms, _, out, _ = time_solver(blp, torch, db, 3, 1, pivot_rule=blp.BLP_RULE_RPC, seed=seed)
+    st = out["status"][:K].cpu().numpy()
+    it = out["iters"][:K].cpu().numpy().astype(np.int64)
+    ob = out["obj"][:K].cpu().numpy()
+    rel = np.abs(ob - obj_lpc) / np.maximum(1.0, np.abs(obj_lpc))
+    rate = K / (ms / 1e3)
+    return {"lps": K, "seed": seed,
+            "lpc": {"lps_per_s": round(rate_lpc, 1), "pivots_per_lp": round(float(iters_lpc.mean()), 3)},
+            "rpc": {"lps_per_s": round(rate, 1), "ms": round(ms, 3), "pivots_per_lp": round(float(it.mean()), 3),
+                    "statuses": np.bincount(st, minlength=5).tolist()},
+            "lpc_over_rpc": round(rate_lpc / rate, 3),
+            "max_obj_relerr_rpc_vs_lpc": float(rel[st == 0].max()) if (st == 0).any() else None}
 
 
 def layout_ablation(blp, torch, lpgen, K=512) -> dict:
