@@ -566,9 +566,10 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
 // the bins of a mixed batch are small, each kernel's duration is set by its
 // slowest LP, and run one after another they leave most of the GPU idle.  A
 // uniform batch has one dominant class, and there the fork and join would
-// only add their own latency.
+// only add their own latency.  A captured sequence (graph mode) keeps every
+// class on the capturing stream.
 static constexpr int64_t kForkMinLps = 2048;
-static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s) {
+static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s, bool capturing = false) {
     const int nreg = h->nreg;
     const int64_t K = sp.P.count;
     KParams P = sp.P;
@@ -578,7 +579,7 @@ static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s) 
         if (sp.maybe[v]) cls.push_back(v);
     if (sp.any_simplex) cls.push_back(nreg);
     const int nc = (int)cls.size();
-    const bool forked = nc > 1 && !sp.uni && K >= kForkMinLps;
+    const bool forked = !capturing && nc > 1 && !sp.uni && K >= kForkMinLps;
     const int nf = forked ? std::min(nc - 1, (int)blp_handle_s::kForks) : 0;
     if (forked) {
         HIP_TRY(h, h->ensure_forks());
@@ -720,7 +721,7 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
             hipGraph_t g = nullptr;
             HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             blp_error ce = enqueue_binning(h, sp, cs);
-            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, cs);
+            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, cs, true);
             if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, cs);
             hipError_t he = hipStreamEndCapture(cs, &g);
             if (ce != BLP_SUCCESS) {

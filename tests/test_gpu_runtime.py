@@ -203,8 +203,9 @@ def test_row_major_workspace_identical():
 def test_mixed_batch_classes_run_concurrently():
     # A mixed batch of at least 2,048 LPs runs its kernel classes on forked
     # streams: every LP as the oracle solves it (all of them, m = n in
-    # 20..150 over several register variants), and graph replays of the same
-    # forked launch sequence identical to the eager solve.
+    # 20..150 over several register variants), and graph replays (the
+    # captured sequence keeps the classes on one stream) identical to the
+    # eager solve.
     import torch
 
     import oracle
