@@ -155,6 +155,45 @@ __global__ void __launch_bounds__(256) scatter_kernel(int64_t count, int nbins, 
     }
 }
 
+// Largest-first work lists.  A persistent launch pops its bin in list order,
+// and lasts as long as its busiest workgroup: with the long LPs taken first
+// and the short ones filling in at the end, the workgroups finish close
+// together (list scheduling, longest first).  Work of an LP is estimated as
+// pivots x entries per pivot, (m + n)(m + 2)(n + m + 1); LPs are ordered by
+// half-octave buckets of it (within a bucket, in scatter order).
+constexpr int kWorkBuckets = 64;
+__device__ __forceinline__ int work_bucket(const KParams& P, int64_t k) {
+    const uint64_t m = (uint32_t)P.m[k], n = (uint32_t)P.n[k];  // m, n >= 0 (checked on the host)
+    const uint64_t w = (m + n) * (m + 2) * (n + m + 1) + 1;
+    const int e = 63 - __clzll((long long)w);
+    const int b = 2 * e + (e > 0 ? (int)((w >> (e - 1)) & 1) : 0);
+    return b < kWorkBuckets - 1 ? b : kWorkBuckets - 1;
+}
+__global__ void __launch_bounds__(1024) order_bins_kernel(KParams P, const int32_t* bin_count,
+                                                          const int32_t* bin_off, const int32_t* list,
+                                                          int32_t* out) {
+    __shared__ int pos[kWorkBuckets];
+    const int b = blockIdx.x;  // one workgroup per bin
+    const int len = bin_count[b], off = bin_off[b];
+    for (int i = threadIdx.x; i < kWorkBuckets; i += blockDim.x) pos[i] = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) atomicAdd(&pos[work_bucket(P, list[off + q])], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // start of each bucket, largest bucket first
+        int acc = off;
+        for (int i = kWorkBuckets - 1; i >= 0; --i) {
+            const int c = pos[i];
+            pos[i] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+        const int32_t k = list[off + q];
+        out[atomicAdd(&pos[work_bucket(P, k)], 1)] = k;
+    }
+}
+
 // Eq. (7): maximise c.x over [l, u]: x_i = l_i where c_i < 0, else u_i; the
 // value is the sequential fused multiply-add sum in increasing i.
 __global__ void hyperbox_kernel(KParams P) {
@@ -342,6 +381,11 @@ hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const 
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, nbins, binid, bin_off,
                        bin_fill, list);
+    return hipGetLastError();
+}
+hipError_t launch_order_bins(const KParams& P, int nbins, const int32_t* bin_count, const int32_t* bin_off,
+                             const int32_t* list, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(order_bins_kernel, dim3((unsigned)nbins), dim3(1024), 0, s, P, bin_count, bin_off, list, out);
     return hipGetLastError();
 }
 static unsigned grid_for(int64_t items, int per_block, int64_t cap) {

@@ -36,6 +36,10 @@ hipError_t launch_bin_offsets(const int32_t* stripes, int32_t* bin_count, int32_
                               hipStream_t s);
 hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const int32_t* bin_off, int32_t* bin_fill,
                           int32_t* list, hipStream_t s);
+// Non-uniform batches: copy each bin's segment of `list` into `out` with the
+// LPs of most estimated work first (one workgroup per bin).
+hipError_t launch_order_bins(const KParams& P, int nbins, const int32_t* bin_count, const int32_t* bin_off,
+                             const int32_t* list, int32_t* out, hipStream_t s);
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s);
 hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,
                                    hipStream_t s);

@@ -75,6 +75,7 @@ struct blp_handle_s {
     DevBuf meta;     // m, n, kind (int32) + a_off, row_off, col_off (int64) for non-uniform batches
     DevBuf counters; // bin_count, bin_fill, bin_head, bin_off (4 x nbins int32), striped bin counters
     DevBuf binid, list;
+    DevBuf olist;  // non-uniform batches: the work lists in largest-first order (what the kernels pop)
     DevBuf ws;       // streaming-kernel workspace
     DevBuf own_status, own_iters, own_obj, own_x, own_y;
     // last solve
@@ -266,6 +267,7 @@ void blp_destroy(blp_handle h) {
     h->counters.release();
     h->binid.release();
     h->list.release();
+    h->olist.release();
     h->ws.release();
     h->own_status.release();
     h->own_iters.release();
@@ -479,6 +481,10 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         HIP_TRY(h, h->binid.reserve(sizeof(int32_t) * K));
         HIP_TRY(h, h->list.reserve(sizeof(int32_t) * K));
         P.list = h->list.as<int32_t>();
+        if (!uni) {
+            HIP_TRY(h, h->olist.reserve(sizeof(int32_t) * K));
+            P.list = h->olist.as<int32_t>();
+        }
     }
 
     // Which register variants can receive an LP?  For a uniform simplex batch
@@ -556,6 +562,11 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
     HIP_TRY(h, launch_scatter(sp.P.count, nbins, h->binid.as<int32_t>(), sp.P.bin_off, bin_fill,
                               h->list.as<int32_t>(), s));
+    // a uniform batch has one cost per bin; otherwise the kernels pop the
+    // bins largest first
+    if (!sp.uni)
+        HIP_TRY(h, launch_order_bins(sp.P, nbins, bin_count, sp.P.bin_off, h->list.as<int32_t>(),
+                                     h->olist.as<int32_t>(), s));
     HIP_TRY(h, h->mark(nbins, false, s));
     return BLP_SUCCESS;
 }
