@@ -256,9 +256,14 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             // A wave streams U columns per step (j0 + u NW), all their loads
             // issued before any is used: with one column per step each wave
             // had QM loads in flight and the update was bound by memory
-            // latency, not bandwidth.
+            // latency, not bandwidth.  Tableaux of 255..510 rows (QM = 8)
+            // keep 32 loads in flight per lane: their launches always have
+            // LPs (no register tile holds them) and the largest LP of a batch
+            // sets its duration.  Smaller tableaux keep 8, since a launch of
+            // theirs may find its bin empty and the extra VGPRs (one
+            // workgroup per CU) would hold CUs the register kernels need.
             const bool skip_art = mode == 2;
-            constexpr int U = QM >= 8 ? 1 : 8 / QM;
+            constexpr int U = QM == 8 ? 4 : QM >= 8 ? 1 : 8 / QM;
             for (int j0 = wave; j0 < C; j0 += NW * U) {
                 bool live[U];
                 double v[U][QM];
