@@ -45,16 +45,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_solver(blp, torch, db, steps, warmup, profile=True, **kw):
-    """Warm up, then time `steps` solves enqueued back to back on one stream
-    (one synchronisation at each end); returns (ms per step, per-class kernel
-    ms of the last timed step from the HIP events the library records around
-    each kernel class (zeros without `profile`), last outputs, bins)."""
+def time_solver(blp, torch, db, steps, warmup, profile=True, warm_ms=0.0, **kw):
+    """Warm up (`warmup` solves, and with `warm_ms` > 0 at least that much wall
+    time, synchronising after 1, 2, 4, ... up to 16 solves), then time `steps` solves enqueued
+    back to back on one stream (one synchronisation at each end); returns (ms
+    per step, per-class kernel ms of the last timed step from the HIP events
+    the library records around each kernel class (zeros without `profile`),
+    last outputs, bins)."""
     s = blp.Solver(profile=profile, **kw)
     stream = torch.cuda.Stream()
     out = None  # output tensors: allocated by the first solve, reused by every later one
     for _ in range(warmup):
         out = s.solve(db, stream=stream, outputs=out)
+    if warm_ms > 0:
+        w0, n = time.perf_counter(), 1
+        while (time.perf_counter() - w0) * 1e3 < warm_ms:
+            for _ in range(n):
+                out = s.solve(db, stream=stream, outputs=out)
+            torch.cuda.synchronize()
+            n = min(16, 2 * n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -454,14 +463,17 @@ def bench_classes(blp, torch, lpgen) -> dict:
         db = blp.DeviceBatch.from_host(hb)
         # short classes: enough warm-up and timed steps to cover tens of ms
         # (3 steps of < 1 ms right after the CPU-only input generation
-        # measured the GPU's ramp-up, not the solve)
+        # measured the GPU's ramp-up, not the solve: the warm-up also runs
+        # for at least 100 ms of wall time)
         # (steps timed without the per-class profiling events, which add
         # their own packets to every launch; kernel times from one profiled
         # solve)
         ms1, kms, _, _ = time_solver(blp, torch, db, 1, 1)
-        steps = max(3, min(200, int(np.ceil(40.0 / max(ms1, 1e-3)))))
-        warm = max(1, min(100, int(np.ceil(20.0 / max(ms1, 1e-3)))))
-        ms, _, out, _ = time_solver(blp, torch, db, steps, warm, profile=False)
+        # (at most 64 steps in flight: with a few hundred small solves
+        # enqueued back to back the HIP runtime's enqueue itself stalls)
+        steps = max(3, min(64, int(np.ceil(40.0 / max(ms1, 1e-3)))))
+        warm = max(1, min(32, int(np.ceil(20.0 / max(ms1, 1e-3)))))
+        ms, _, out, _ = time_solver(blp, torch, db, steps, warm, profile=False, warm_ms=100.0)
         entry_steps = steps
         st = np.bincount(out["status"][:n_batch].cpu().numpy(), minlength=5).tolist()
         entry = {"lps": n_batch, "persistent_lps_per_s": round(n_batch / (ms / 1e3), 1), "ms": round(ms, 3),
