@@ -53,8 +53,10 @@ int shared_threads();
 void shared_shape(int* rows, int* cols);
 
 // Streaming kernel (simplex_gm.hip).
-hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s);
-const void* gm_kernel_ptr(int ld);
+// deep: the launch's bin is known not to be empty (32 loads in flight per
+// lane for tableaux of 129..256 rows as well).
+hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s, bool deep = false);
+const void* gm_kernel_ptr(int ld, bool deep = false);
 int gm_threads();
 size_t gm_lds_bytes_host(int ld, int cols);
 

@@ -301,6 +301,7 @@ struct SolvePlan {
     bool uni = false, any_simplex = false, any_box = false, box_only_uniform = false;
     int64_t n_box = 0;
     int gm_ld = 0, gm_cols = 0, gm_workers = 0;
+    bool gm_deep = false;  // some LP cannot be held by any register tile: the streaming bin is not empty
     size_t gm_lds = 0;
     std::vector<char> maybe;  // register variants that can receive LPs
 };
@@ -327,6 +328,16 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             if (h->remap[v] >= h->nreg) return true;
         return false;
     }();
+    sp.gm_deep = false;
+    // no register tile holds the LP even without artificial columns
+    auto sure_stream = [&](int m, int n) {
+        if (h->opt.variant == -2) return true;
+        for (int v = 0; v < h->nreg; ++v) {
+            if (h->opt.variant >= 0 && v != h->opt.variant) continue;
+            if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + 1) return false;
+        }
+        return true;
+    };
     auto sure_register = [&](int m, int n) {
         if (stream_all || h->opt.variant == -2 || remap_streams) return false;
         for (int v = 0; v < h->nreg; ++v) {
@@ -347,6 +358,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             max_cols = std::max(max_cols, n + m + 1);
             max_slot = std::max<int64_t>(max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
             if (!sure_register(m, n)) ++n_may_stream;
+            if (sure_stream(m, n)) sp.gm_deep = true;
         } else if (kd == BLP_KIND_HYPERBOX) {
             if (m != 0 || n < 1) return fail(h, BLP_ERR_ARG, "LP %lld: hyperbox LP needs m == 0 and n >= 1", (long long)k);
             any_box = true;
@@ -518,7 +530,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         sp.gm_cols = max_cols;
         sp.gm_lds = gm_lds_bytes_host(sp.gm_ld, sp.gm_cols);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld), gm_threads(), sp.gm_lds) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld, sp.gm_deep), gm_threads(), sp.gm_lds) !=
                 hipSuccess ||
             occ < 1)
             occ = 1;
@@ -607,7 +619,7 @@ static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s, 
         if (v < nreg) {
             HIP_TRY(h, h->variants[v].launch(Q, (int)std::min<int64_t>(h->reg_workers[v], K), st));
         } else {
-            HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st));
+            HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st, sp.gm_deep));
         }
         HIP_TRY(h, h->mark(v, false, st));
     }
@@ -651,11 +663,11 @@ static blp_error enqueue_baseline(blp_handle h, SolvePlan& sp, hipStream_t s) {
             const int grid = (int)std::min<int64_t>(chunk, nv - first);
             if (v == nreg) {
                 if (mode == BLP_MODE_GRID) {
-                    HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s));
+                    HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s, sp.gm_deep));
                 } else {
                     for (int64_t q = first; q < first + grid; ++q) {
                         Q.direct_first = q;
-                        HIP_TRY(h, launch_gm(Q, 1, sp.gm_lds, s));
+                        HIP_TRY(h, launch_gm(Q, 1, sp.gm_lds, s, sp.gm_deep));
                     }
                 }
             } else {
@@ -679,7 +691,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
                                (uint64_t)(uintptr_t)P.y, (uint64_t)(uintptr_t)P.list, (uint64_t)(uintptr_t)P.bin_len,
                                (uint64_t)(uintptr_t)P.ws, (uint64_t)P.ws_slot, (uint64_t)P.ws_ld,
                                (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)h->binid.p,
-                               (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers};
+                               (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers, (uint64_t)sp.gm_deep};
     for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
     g.push_back((uint64_t)P.pivot_rule);
     g.push_back((uint64_t)P.layout);
@@ -1206,7 +1218,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
                 if (w < nreg) {
                     HIP_TRY(h, h->variants[w].launch(Q, (int)std::min<int64_t>(h->reg_workers[w], S), s));
                 } else {
-                    HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, S), sp.gm_lds, s));
+                    HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, S), sp.gm_lds, s, sp.gm_deep));
                 }
                 HIP_TRY(h, hipEventRecord(e1, s));
                 HIP_TRY(h, hipEventSynchronize(e1));

@@ -36,7 +36,9 @@ __host__ __device__ inline size_t gm_lds_bytes(int ld, int cols) {
 // the same thread mapping, so the column reads and the update are strided
 // across lanes: the non-coalesced variant of Sec. 4.3's comparison, kept for
 // the layout measurement; results are identical.
-template <int NW, int QM, bool RM>
+// DEEP (instantiated with QM = 4 only): 32 loads in flight per lane in the
+// update, for launches whose bin cannot be empty.
+template <int NW, int QM, bool RM, bool DEEP = false>
 __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     constexpr int NT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -259,11 +261,12 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             // latency, not bandwidth.  Tableaux of 255..510 rows (QM = 8)
             // keep 32 loads in flight per lane: their launches always have
             // LPs (no register tile holds them) and the largest LP of a batch
-            // sets its duration.  Smaller tableaux keep 8, since a launch of
-            // theirs may find its bin empty and the extra VGPRs (one
-            // workgroup per CU) would hold CUs the register kernels need.
+            // sets its duration.  Smaller tableaux keep 8 unless the host
+            // knows the bin is not empty (DEEP): a launch that finds its bin
+            // empty would otherwise hold CUs the register kernels need with
+            // its extra VGPRs (one workgroup per CU).
             const bool skip_art = mode == 2;
-            constexpr int U = QM == 8 ? 4 : QM >= 8 ? 1 : 8 / QM;
+            constexpr int U = DEEP ? 32 / QM : QM == 8 ? 4 : QM >= 8 ? 1 : 8 / QM;
             for (int j0 = wave; j0 < C; j0 += NW * U) {
                 bool live[U];
                 double v[U][QM];
@@ -313,30 +316,32 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
     }
 }
 
-template <int QM>
+template <int QM, bool DEEP = false>
 static hipError_t launch_gm_q(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
     if (P.layout == 1)
-        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, true>), dim3(grid), dim3(512), lds_bytes, s, P);
+        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, true, DEEP>), dim3(grid), dim3(512), lds_bytes, s, P);
     else
-        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, false>), dim3(grid), dim3(512), lds_bytes, s, P);
+        hipLaunchKernelGGL((simplex_gm_kernel<8, QM, false, DEEP>), dim3(grid), dim3(512), lds_bytes, s, P);
     return hipGetLastError();
 }
 static int gm_chunks(int ld) { return ld <= 64 ? 1 : ld <= 128 ? 2 : ld <= 256 ? 4 : ld <= 512 ? 8 : ld <= 1024 ? 16 : 32; }
-hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s, bool deep) {
     switch (gm_chunks(P.ws_ld)) {
         case 1: return launch_gm_q<1>(P, grid, lds_bytes, s);
         case 2: return launch_gm_q<2>(P, grid, lds_bytes, s);
-        case 4: return launch_gm_q<4>(P, grid, lds_bytes, s);
+        case 4: return deep ? launch_gm_q<4, true>(P, grid, lds_bytes, s) : launch_gm_q<4>(P, grid, lds_bytes, s);
         case 8: return launch_gm_q<8>(P, grid, lds_bytes, s);
         case 16: return launch_gm_q<16>(P, grid, lds_bytes, s);
         default: return launch_gm_q<32>(P, grid, lds_bytes, s);
     }
 }
-const void* gm_kernel_ptr(int ld) {
+const void* gm_kernel_ptr(int ld, bool deep) {
     switch (gm_chunks(ld)) {
         case 1: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 1, false>);
         case 2: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 2, false>);
-        case 4: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4, false>);
+        case 4:
+            return deep ? reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4, false, true>)
+                        : reinterpret_cast<const void*>(&simplex_gm_kernel<8, 4, false>);
         case 8: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 8, false>);
         case 16: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 16, false>);
         default: return reinterpret_cast<const void*>(&simplex_gm_kernel<8, 32, false>);
