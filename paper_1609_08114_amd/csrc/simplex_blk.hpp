@@ -393,6 +393,15 @@ simplex_blk_kernel(KParams P) {
                     T[r][c] = v;
                 }
             }
+            // the finished tile and the finiteness flag are computed here:
+            // otherwise they sink into the pivot loop, and the raw tile and
+            // every input of the selects above stay live across Step 1 (the
+            // 160 x 160 tile then spilled)
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) __asm__ volatile("" : "+v"(T[r][c]));
+            __asm__ volatile("" : "+v"(bad));
         }
         // register mirrors (identical in every wave)
 #pragma unroll
