@@ -368,5 +368,133 @@ def pin_monotone(L, seed=13):
         assert rel_err(prev, full["obj"]) <= 1e-12
 
 
+# --------------------------------------------------------------------------
+# The batch driver: packed layout with arbitrary offsets, mixed kinds
+# --------------------------------------------------------------------------
+def _scattered_batch(seed=17):
+    """Mixed simplex / hyperbox LPs (tiny brute-force cases with every
+    outcome, diagonal closed forms, generator LPs of both types, non-finite
+    members) stored in a permuted order at gapped, non-monotone offsets; the
+    gaps hold NaN so that a read at a wrong offset changes the outcome.
+    Returns (lps, batch arrays, expected (status, obj) per LP or None)."""
+    rng = np.random.default_rng(seed)
+    lps, expect = [], []
+    while len(lps) < 24:  # tiny LPs, brute force, every outcome
+        m, n = int(rng.integers(1, 5)), int(rng.integers(1, 4))
+        A = rng.integers(-3, 7, size=(m, n)).astype(float)
+        b = rng.integers(-4, 11, size=m).astype(float)
+        c = rng.integers(-2, 6, size=n).astype(float)
+        sense = rng.integers(0, 2, size=m).astype(np.int8)
+        lps.append({"A": A, "b": b, "c": c, "sense": sense})
+        expect.append(brute_force(A, b, sense, c))
+    for _ in range(6):  # diagonal: opt = sum c_j b_j / a_jj
+        n = int(rng.integers(1, 12))
+        a, b, c = rng.uniform(1, 10, n), rng.uniform(10, 100, n), rng.uniform(1, 10, n)
+        lps.append({"A": np.diag(a), "b": b, "c": c, "sense": np.zeros(n, np.int8)})
+        expect.append((0, float(np.sum(c * b / a))))
+    g1 = lpgen.config(1, range(4))
+    g4 = lpgen.config(4, [i for i in range(400) if lpgen.config(4, [i]).m[0] <= 24][:6])
+    for bt in (g1, g4):
+        for k in range(bt.count):
+            d = bt.lp(k)
+            lps.append({kk: np.array(v) for kk, v in d.items() if kk in ("A", "b", "c", "sense", "l", "u")})
+            expect.append(None)
+    for t in range(8):  # hyperbox: Eq. (7) against box-vertex enumeration
+        n = int(rng.integers(1, 7))
+        c, lo, hi = rng.normal(size=n), rng.uniform(-10, -1, n), rng.uniform(1, 10, n)
+        if t == 6:
+            lo[0], hi[0] = 2.0, 1.0  # empty box
+        lps.append({"c": c, "l": lo, "u": hi})
+        if t == 6:
+            expect.append((1, -np.inf))
+        else:
+            verts = np.array(list(itertools.product(*zip(lo, hi))))
+            expect.append((0, float((verts @ c).max())))
+    lps.append({"A": np.array([[1.0, np.nan]]), "b": np.array([1.0]), "c": np.array([1.0, 1.0]),
+                "sense": np.zeros(1, np.int8)})
+    expect.append((4, np.nan))
+    lps.append({"c": np.array([np.nan, 1.0]), "l": np.array([-1.0, -1.0]), "u": np.array([1.0, 1.0])})
+    expect.append((4, np.nan))
+    K = len(lps)
+    order = rng.permutation(K)  # storage order differs from LP order
+    m = np.array([0 if "l" in d else d["A"].shape[0] for d in lps], np.int32)
+    n = np.array([len(d["c"]) for d in lps], np.int32)
+    kind = np.array([1 if "l" in d else 0 for d in lps], np.int32)
+    a_off, row_off, col_off = (np.zeros(K, np.int64) for _ in range(3))
+    pa = pr = pc = 0
+    for k in order:
+        pa += int(rng.integers(0, 5))
+        pr += int(rng.integers(0, 4))
+        pc += int(rng.integers(0, 4))
+        a_off[k], row_off[k], col_off[k] = pa, pr, pc
+        pa += int(m[k]) * int(n[k])
+        pr += int(m[k])
+        pc += int(n[k])
+    A = np.full(pa + 3, np.nan)
+    b = np.full(pr + 3, np.nan)
+    sense = np.full(pr + 3, 1, np.int8)
+    c = np.full(pc + 3, np.nan)
+    l = np.full(pc + 3, np.nan)
+    u = np.full(pc + 3, np.nan)
+    for k, d in enumerate(lps):
+        co, nn = int(col_off[k]), int(n[k])
+        c[co:co + nn] = d["c"]
+        if kind[k]:
+            l[co:co + nn], u[co:co + nn] = d["l"], d["u"]
+        else:
+            ao, ro, mm = int(a_off[k]), int(row_off[k]), int(m[k])
+            A[ao:ao + mm * nn] = d["A"].ravel()
+            b[ro:ro + mm] = d["b"]
+            sense[ro:ro + mm] = d["sense"]
+    return lps, (K, m, n, kind, a_off, row_off, col_off, A, b, sense, c, l, u), expect
+
+
+def pin_batch_driver(L):
+    """oracle_batch on a scattered batch: every LP's status, iterations,
+    objective, x and y equal (bit for bit) the single-LP routines' results at
+    that LP's own offsets, outcomes match brute force / closed forms, and no
+    output position outside the LPs' ranges is written."""
+    import ctypes
+    lps, arrs, expect = _scattered_batch()
+    K, m, n, kind, a_off, row_off, col_off, A, b, sense, c, l, u = arrs
+    SENT = 1234.5
+    st = np.full(K, -7, np.int32)
+    it = np.full(K, -7, np.int32)
+    ob = np.full(K, SENT)
+    # outputs padded past both packed ranges, so that a driver writing at the
+    # wrong offsets stays inside the arrays (and is caught by the sentinel)
+    pad = max(c.shape[0], b.shape[0]) + 64
+    x = np.full(pad, SENT)
+    y = np.full(pad, SENT)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    L.oracle_batch(K, P(m), P(n), P(kind), P(a_off), P(row_off), P(col_off), P(A), P(b), P(sense), P(c),
+                   P(l), P(u), ctypes.byref(oracle.Opts(0, 0, 0.0, 0.0, 0.0)), P(st), P(it), P(ob), P(x), P(y))
+    xw = np.zeros(x.shape[0], bool)
+    yw = np.zeros(y.shape[0], bool)
+    for k, d in enumerate(lps):
+        co, nn = int(col_off[k]), int(n[k])
+        if kind[k]:
+            r = oracle.hyperbox(d["c"], d["l"], d["u"], library=L)
+            r["iters"], r["y"] = 0, np.zeros(0)
+        else:
+            r = oracle.solve(d["A"], d["b"], d["c"], d["sense"], library=L)
+        ro, mm = int(row_off[k]), int(m[k])
+        assert st[k] == r["status"] and it[k] == r["iters"], (k, st[k], r["status"], it[k], r["iters"])
+        assert np.array_equal(np.array([ob[k]]).view(np.int64), np.array([r["obj"]]).view(np.int64)), k
+        assert np.array_equal(x[co:co + nn].view(np.int64), r["x"].view(np.int64)), k
+        if not kind[k]:
+            assert np.array_equal(y[ro:ro + mm].view(np.int64), r["y"].view(np.int64)), k
+            yw[ro:ro + mm] = True
+        xw[co:co + nn] = True
+        if expect[k] is not None:
+            est, eob = expect[k]
+            assert st[k] == est, (k, st[k], est)
+            if est == 0:
+                assert rel_err(ob[k], eob) <= 1e-8, (k, ob[k], eob)
+    assert (x[~xw] == SENT).all() and (y[~yw] == SENT).all(), "output written outside the LPs' ranges"
+    assert set(np.unique(st)) >= {0, 1, 2, 4}
+
+
 ALL_PINS = [pin_bruteforce, pin_bruteforce_float, pin_closed_forms, pin_duality, pin_klee_minty,
-            pin_statuses, pin_degenerate_cycling, pin_hyperbox, pin_external, pin_monotone]
+            pin_statuses, pin_degenerate_cycling, pin_hyperbox, pin_external, pin_monotone,
+            pin_batch_driver]

@@ -33,6 +33,10 @@ MUTANTS = {
     "no_anticycling": ("if (degen_run >= bland_after) {", "if (0) {"),
     "hyperbox_swapped": ("x[i] = c[i] < 0.0 ? l[i] : u[i];", "x[i] = c[i] < 0.0 ? u[i] : l[i];"),
     "hyperbox_tie_lower": ("x[i] = c[i] < 0.0 ? l[i] : u[i];", "x[i] = c[i] <= 0.0 ? l[i] : u[i];"),
+    "batch_y_at_col_off": ("x + col_off[k], y + row_off[k]", "x + col_off[k], y + col_off[k]"),
+    "batch_a_at_row_off": ("A + a_off[k], b + row_off[k]", "A + row_off[k], b + row_off[k]"),
+    "batch_kind_inverted": ("if (kind[k] == 1) {", "if (kind[k] != 0 && m[k] != 0) {"),
+    "batch_iters_not_reset": ("            iters[k] = 0;\n", ""),
 }
 
 
