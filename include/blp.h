@@ -27,7 +27,9 @@
  *     "host" pointers are ordinary CPU memory.
  *   - Work is ordered on the HIP stream passed in (NULL = default stream);
  *     the caller keeps every input alive until that stream has passed the
- *     call.
+ *     call.  A handle's calls reuse its device buffers: a call on another
+ *     stream than the handle's previous call first waits (on the device)
+ *     for that call's work.
  */
 #ifndef BLP_H
 #define BLP_H
@@ -163,8 +165,9 @@ blp_error blp_options_default(blp_options* opt);
 blp_error blp_create(blp_handle* out, const blp_options* opt);
 
 /* Solve every LP of the batch (stream-ordered; returns before the GPU is
- * done).  Sizes: simplex LPs need 1 <= m <= 2046 and 1 <= n, with
- * n + (number of rows whose "<=" right-hand side is negative) + 1 <= 4096;
+ * done).  Sizes: simplex LPs need 1 <= m <= 2046 and 1 <= n with
+ * n + m + 1 <= 4096 (the widest condensed tableau, one column per
+ * structural variable and per possible artificial variable, plus the rhs);
  * hyperbox LPs need 1 <= n.  Violations found on the host return
  * BLP_ERR_ARG / BLP_ERR_TOO_LARGE before any launch.  `out` may be NULL.
  * The handle remembers the batch and output pointers for blp_backward and

@@ -61,6 +61,24 @@ struct DevBuf {
     }
 };
 
+// Bump allocator over one caller-independent device region (the static
+// scratch array of the allocation-free entry point): hands out 256-byte
+// aligned pieces, never frees.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    void* take(size_t bytes) {
+        const size_t at = (used + 255) & ~size_t(255);
+        if (at > cap || bytes > cap - at) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+    size_t left() const {
+        const size_t at = (used + 255) & ~size_t(255);
+        return at < cap ? cap - at : 0;
+    }
+};
+
 }  // namespace
 
 struct blp_handle_s {
@@ -82,6 +100,11 @@ struct blp_handle_s {
     bool solved = false;
     KParams last{};
     hipStream_t last_stream = nullptr;
+    // Every call's device work reuses the handle's buffers.  order_ev is
+    // recorded at the end of each call's work (unless that stream was being
+    // captured); a call on another stream first waits for it.
+    hipEvent_t order_ev = nullptr;
+    bool order_pending = false;
     std::vector<int32_t> h_m, h_n, h_kind;
     std::vector<int64_t> h_row_off, h_col_off, h_a_off;
     int64_t count = 0;
@@ -102,7 +125,8 @@ struct blp_handle_s {
     static constexpr int kForks = 3;
     hipStream_t fork[kForks] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kForks] = {nullptr, nullptr, nullptr};
-    hipError_t ensure_forks() {
+    // created once, by blp_create (never inside a capture or a solve)
+    hipError_t create_forks() {
         for (int i = 0; i < kForks; ++i) {
             if (!fork[i]) {
                 hipError_t e = hipStreamCreateWithFlags(&fork[i], hipStreamNonBlocking);
@@ -126,6 +150,8 @@ struct blp_handle_s {
     // profiling events: one start/stop pair per kernel class (+1 for binning)
     std::vector<hipEvent_t> ev0, ev1;
     std::vector<char> ev_used;
+    // created by blp_create (all classes + binning); later calls only reset
+    // the used flags
     hipError_t ensure_events(int n) {
         while ((int)ev0.size() < n) {
             hipEvent_t a, b;
@@ -145,6 +171,29 @@ struct blp_handle_s {
         return hipEventRecord(start ? ev0[cls] : ev1[cls], s);
     }
 };
+
+static blp_error fail(blp_handle h, blp_error code, const char* fmt, ...);
+
+// Order this call's work after the previous call's (see order_ev).
+static hipError_t begin_call(blp_handle h, hipStream_t s) {
+    if (h->order_pending && s != h->last_stream) return hipStreamWaitEvent(s, h->order_ev, 0);
+    return hipSuccess;
+}
+static hipError_t end_call(blp_handle h, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    h->last_stream = s;
+    h->order_pending = false;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    e = hipEventRecord(h->order_ev, s);
+    h->order_pending = e == hipSuccess;
+    return e;
+}
+// Host wait for the last call's device work.
+static hipError_t wait_last(blp_handle h) {
+    return h->order_pending ? hipEventSynchronize(h->order_ev) : hipStreamSynchronize(h->last_stream);
+}
 
 static blp_error fail(blp_handle h, blp_error code, const char* fmt, ...) {
     if (h) {
@@ -237,6 +286,16 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
     if (hipMalloc(&h->timers, TM_SLOTS * sizeof(unsigned long long)) == hipSuccess)
         (void)hipMemset(h->timers, 0, TM_SLOTS * sizeof(unsigned long long));
 #endif
+    // Streams and events the solves use are made here, once: never lazily
+    // inside a solve (which may run under a caller's stream capture) and
+    // never by the allocation-free entry point.
+    hipError_t ce = h->create_forks();
+    if (ce == hipSuccess) ce = hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming);
+    if (ce == hipSuccess && h->opt.profile) ce = h->ensure_events(h->nreg + 3);
+    if (ce != hipSuccess) {
+        blp_destroy(h);
+        return ce == hipErrorOutOfMemory ? BLP_ERR_NOMEM : BLP_ERR_HIP;
+    }
     *out = h;
     return BLP_SUCCESS;
 }
@@ -263,6 +322,20 @@ void blp_destroy(blp_handle h) {
         (void)hipFree(h->timers);
     }
 #endif
+    // the captured launch sequence and the streams/events go before the
+    // buffers its kernels reference
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->cap_stream = nullptr;
+    for (int i = 0; i < blp_handle_s::kForks; ++i) {
+        if (h->fork[i]) (void)hipStreamDestroy(h->fork[i]);
+        if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->order_ev) (void)hipEventDestroy(h->order_ev);
+    for (auto e : h->ev0) (void)hipEventDestroy(e);
+    for (auto e : h->ev1) (void)hipEventDestroy(e);
     h->meta.release();
     h->counters.release();
     h->binid.release();
@@ -281,15 +354,7 @@ void blp_destroy(blp_handle h) {
         h->pin_in[i].release();
         h->pin_out[i].release();
     }
-    for (auto e : h->ev0) (void)hipEventDestroy(e);
-    for (auto e : h->ev1) (void)hipEventDestroy(e);
-    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    for (int i = 0; i < blp_handle_s::kForks; ++i) {
-        if (h->fork[i]) (void)hipStreamDestroy(h->fork[i]);
-        if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
-    }
-    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    h->shared_ctr.release();
     delete h;
 }
 
@@ -304,13 +369,38 @@ struct SolvePlan {
     bool gm_deep = false;  // some LP cannot be held by any register tile: the streaming bin is not empty
     size_t gm_lds = 0;
     std::vector<char> maybe;  // register variants that can receive LPs
+    // device buffers of this solve (the handle's own, or carved from an arena)
+    int32_t* counters = nullptr;
+    int32_t* binid = nullptr;
+    int32_t* list = nullptr;   // unordered work lists (scatter output)
+    int32_t* olist = nullptr;  // largest-first work lists (non-uniform batches)
 };
+
+// A device buffer for one solve: the handle's growable buffer `own`, or,
+// with an arena (the allocation-free entry point), a piece of the arena.
+#define BUF_TRY(h, arena, own, bytes, ptr)                                                              \
+    do {                                                                                             \
+        const size_t want_ = (bytes);                                                                \
+        if (arena) {                                                                                 \
+            void* p_ = (arena)->take(want_);                                                         \
+            if (!p_)                                                                                 \
+                return fail(h, BLP_ERR_TOO_LARGE,                                                    \
+                            "static scratch of %zu bytes exhausted (%s needs %zu more bytes)",      \
+                            (arena)->cap, #own, want_);                                              \
+            (ptr) = static_cast<decltype(ptr)>(p_);                                                  \
+        } else {                                                                                     \
+            HIP_TRY(h, (own).reserve(want_));                                                        \
+            (ptr) = static_cast<decltype(ptr)>((own).p);                                             \
+        }                                                                                            \
+    } while (0)
 
 // Validation, outputs, metadata upload, workspace sizing.  No kernel launch.
 // stream_all: size the streaming workspace as if every simplex LP could reach
 // the streaming kernel (the autotuner times it on register-variant samples).
+// arena: the allocation-free entry point's scratch (every output must then
+// be given; nothing is allocated).
 static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp,
-                         bool stream_all = false) {
+                         bool stream_all = false, Arena* arena = nullptr) {
     const int64_t K = B->count;
     if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
     const bool uni = B->uniform != 0;
@@ -405,6 +495,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     // ---- outputs
     blp_outputs o{};
     if (out) o = *out;
+    if (arena && (!o.status || !o.iters || !o.obj || !o.x || !o.y))
+        return fail(h, BLP_ERR_ARG, "all five output buffers are required");
     if (!o.status) {
         HIP_TRY(h, h->own_status.reserve(sizeof(int32_t) * K));
         o.status = h->own_status.as<int32_t>();
@@ -436,8 +528,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.ukind = h->h_kind[0];
     if (!uni) {
         const size_t bytes = (size_t)K * (3 * sizeof(int32_t) + 3 * sizeof(int64_t));
-        HIP_TRY(h, h->meta.reserve(bytes));
-        char* base = h->meta.as<char>();
+        char* base = nullptr;
+        BUF_TRY(h, arena, h->meta, bytes, base);
         int64_t* offs = reinterpret_cast<int64_t*>(base);
         int32_t* ints = reinterpret_cast<int32_t*>(base + (size_t)K * 3 * sizeof(int64_t));
         HIP_TRY(h, hipMemcpyAsync(offs, h->h_a_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -477,8 +569,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
 #endif
     const int nreg = h->nreg, nbins = nreg + 2;
     // bin_count, bin_fill, bin_head, bin_off, then the striped bin counters
-    HIP_TRY(h, h->counters.reserve(sizeof(int32_t) * (4 + (size_t)kBinStripes) * nbins));
-    int32_t* bin_count = h->counters.as<int32_t>();
+    BUF_TRY(h, arena, h->counters, sizeof(int32_t) * (4 + (size_t)kBinStripes) * nbins, sp.counters);
+    int32_t* bin_count = sp.counters;
     P.bin_len = bin_count;
     P.bin_head = bin_count + 2 * nbins;
     P.bin_off = bin_count + 3 * nbins;
@@ -490,12 +582,12 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     sp.n_box = n_box;
     sp.box_only_uniform = uni && !any_simplex;
     if (!sp.box_only_uniform) {
-        HIP_TRY(h, h->binid.reserve(sizeof(int32_t) * K));
-        HIP_TRY(h, h->list.reserve(sizeof(int32_t) * K));
-        P.list = h->list.as<int32_t>();
+        BUF_TRY(h, arena, h->binid, sizeof(int32_t) * K, sp.binid);
+        BUF_TRY(h, arena, h->list, sizeof(int32_t) * K, sp.list);
+        P.list = sp.list;
         if (!uni) {
-            HIP_TRY(h, h->olist.reserve(sizeof(int32_t) * K));
-            P.list = h->olist.as<int32_t>();
+            BUF_TRY(h, arena, h->olist, sizeof(int32_t) * K, sp.olist);
+            P.list = sp.olist;
         }
     }
 
@@ -539,8 +631,17 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         // than LPs that can reach the streaming kernel
         sp.gm_workers = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * h->cu_count, n_may_stream));
         const size_t slot = (size_t)max_slot;
-        HIP_TRY(h, h->ws.reserve(sizeof(double) * slot * (size_t)sp.gm_workers));
-        P.ws = h->ws.as<double>();
+        if (arena) {
+            // as many workspace slots as the scratch still holds (fewer
+            // persistent workgroups; the same results)
+            const int64_t fit = (int64_t)(arena->left() / (sizeof(double) * slot));
+            if (fit < 1)
+                return fail(h, BLP_ERR_TOO_LARGE,
+                            "static scratch of %zu bytes cannot hold one streaming workspace slot of %zu bytes",
+                            arena->cap, sizeof(double) * slot);
+            sp.gm_workers = (int)std::min<int64_t>(sp.gm_workers, fit);
+        }
+        BUF_TRY(h, arena, h->ws, sizeof(double) * slot * (size_t)sp.gm_workers, P.ws);
         P.ws_slot = (int64_t)slot;
         P.ws_ld = sp.gm_ld;
         P.ws_cols = sp.gm_cols;
@@ -564,21 +665,19 @@ static VariantTable variant_table(blp_handle h) {
 static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     if (sp.box_only_uniform) return BLP_SUCCESS;
     const int nbins = h->nreg + 2;
-    int32_t* bin_count = h->counters.as<int32_t>();
+    int32_t* bin_count = sp.counters;
     int32_t* bin_fill = bin_count + nbins;
     HIP_TRY(h, h->mark(nbins, true, s));
     // zero the counters and the striped bin counters (bin_off is rewritten)
     int32_t* stripes = bin_count + 4 * nbins;
     HIP_TRY(h, launch_reset(bin_count, (4 + kBinStripes) * nbins, s));
-    HIP_TRY(h, launch_classify(sp.P, variant_table(h), h->binid.as<int32_t>(), stripes, s));
+    HIP_TRY(h, launch_classify(sp.P, variant_table(h), sp.binid, stripes, s));
     HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
-    HIP_TRY(h, launch_scatter(sp.P.count, nbins, h->binid.as<int32_t>(), sp.P.bin_off, bin_fill,
-                              h->list.as<int32_t>(), s));
+    HIP_TRY(h, launch_scatter(sp.P.count, nbins, sp.binid, sp.P.bin_off, bin_fill, sp.list, s));
     // a uniform batch has one cost per bin; otherwise the kernels pop the
     // bins largest first
     if (!sp.uni)
-        HIP_TRY(h, launch_order_bins(sp.P, nbins, bin_count, sp.P.bin_off, h->list.as<int32_t>(),
-                                     h->olist.as<int32_t>(), s));
+        HIP_TRY(h, launch_order_bins(sp.P, nbins, bin_count, sp.P.bin_off, sp.list, sp.olist, s));
     HIP_TRY(h, h->mark(nbins, false, s));
     return BLP_SUCCESS;
 }
@@ -605,28 +704,44 @@ static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s, 
     const bool forked = !capturing && nc > 1 && !sp.uni && K >= kForkMinLps;
     const int nf = forked ? std::min(nc - 1, (int)blp_handle_s::kForks) : 0;
     if (forked) {
-        HIP_TRY(h, h->ensure_forks());
         HIP_TRY(h, hipEventRecord(h->fork_ev, s));
         for (int i = 0; i < nf; ++i) HIP_TRY(h, hipStreamWaitEvent(h->fork[i], h->fork_ev, 0));
     }
-    for (int i = 0; i < nc; ++i) {
+    // launches record their first error; the forks are joined back into s
+    // in every case, so that work already issued on a fork is ordered before
+    // whatever the caller (or the next solve on the handle's buffers) issues
+    // on s next
+    hipError_t err = hipSuccess;
+    const char* what = "";
+    for (int i = 0; i < nc && err == hipSuccess; ++i) {
         const int v = cls[i];
         // the last class (the streaming kernel when present) stays on s
         hipStream_t st = (forked && i < nc - 1) ? h->fork[i % nf] : s;
         KParams Q = P;
         Q.bin = v;
-        HIP_TRY(h, h->mark(v, true, st));
-        if (v < nreg) {
-            HIP_TRY(h, h->variants[v].launch(Q, (int)std::min<int64_t>(h->reg_workers[v], K), st));
-        } else {
-            HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st, sp.gm_deep));
+        err = h->mark(v, true, st);
+        what = "event record";
+        if (err == hipSuccess) {
+            what = "kernel launch";
+            err = v < nreg ? h->variants[v].launch(Q, (int)std::min<int64_t>(h->reg_workers[v], K), st)
+                           : launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st, sp.gm_deep);
         }
-        HIP_TRY(h, h->mark(v, false, st));
+        if (err == hipSuccess) {
+            what = "event record";
+            err = h->mark(v, false, st);
+        }
     }
     for (int i = 0; i < nf; ++i) {
-        HIP_TRY(h, hipEventRecord(h->join_ev[i], h->fork[i]));
-        HIP_TRY(h, hipStreamWaitEvent(s, h->join_ev[i], 0));
+        hipError_t je = hipEventRecord(h->join_ev[i], h->fork[i]);
+        if (je == hipSuccess) je = hipStreamWaitEvent(s, h->join_ev[i], 0);
+        if (err == hipSuccess && je != hipSuccess) {
+            err = je;
+            what = "fork join";
+        }
     }
+    if (err != hipSuccess)
+        return fail(h, err == hipErrorOutOfMemory ? BLP_ERR_NOMEM : BLP_ERR_HIP, "persistent %s: %s (%s)", what,
+                    hipGetErrorString(err), hipGetErrorName(err));
     return BLP_SUCCESS;
 }
 
@@ -690,7 +805,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
                                (uint64_t)(uintptr_t)P.iters, (uint64_t)(uintptr_t)P.obj, (uint64_t)(uintptr_t)P.x,
                                (uint64_t)(uintptr_t)P.y, (uint64_t)(uintptr_t)P.list, (uint64_t)(uintptr_t)P.bin_len,
                                (uint64_t)(uintptr_t)P.ws, (uint64_t)P.ws_slot, (uint64_t)P.ws_ld,
-                               (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)h->binid.p,
+                               (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)sp.binid,
                                (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers, (uint64_t)sp.gm_deep};
     for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
     g.push_back((uint64_t)P.pivot_rule);
@@ -724,6 +839,7 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
         h->solved = true;
         return BLP_SUCCESS;
     }
+    HIP_TRY(h, begin_call(h, s));
     SolvePlan sp;
     blp_error e = prepare(h, B, out, s, sp);
     if (e != BLP_SUCCESS) return e;
@@ -767,10 +883,10 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
         if (e != BLP_SUCCESS) return e;
     }
     HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, end_call(h, s));
 
     h->last = sp.P;
     h->last.direct = 0;
-    h->last_stream = s;
     h->count = K;
     h->uniform = sp.uni;
     h->any_simplex = sp.any_simplex;
@@ -797,6 +913,7 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need m + 2 <= %d and n + n_art + 1 <= %d", rows, cols);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, begin_call(h, s));
     // the tableau width depends on how many rows need an artificial variable;
     // the first objectives tell whether consecutive directions are close
     // enough for warm starts
@@ -871,6 +988,7 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         P.shared_in = 1;
         HIP_TRY(h, launch_reset(P.bin_head, 1, s));
         HIP_TRY(h, h->variants[v].launch(P, (int)std::min<int64_t>(h->reg_workers[v], count), s));
+        HIP_TRY(h, end_call(h, s));
         return BLP_SUCCESS;
     }
     int occ = 0;
@@ -884,6 +1002,7 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     const int grid = (int)std::min<int64_t>(workers, (count + P.chunk - 1) / P.chunk);
     HIP_TRY(h, launch_reset(P.bin_head, 1, s));
     HIP_TRY(h, launch_shared(P, grid, s));
+    HIP_TRY(h, end_call(h, s));
     return BLP_SUCCESS;
 }
 
@@ -928,6 +1047,7 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         if (!h->pipe[i]) HIP_TRY(h, hipStreamCreateWithFlags(&h->pipe[i], hipStreamNonBlocking));
     }
     struct Range { int64_t lo = INT64_MAX, hi = 0; };
+    std::vector<int64_t> order;
     for (int32_t ch = 0; ch < chunks; ++ch) {
         const int64_t k0 = K * ch / chunks, k1 = K * (ch + 1) / chunks, Kc = k1 - k0;
         const int slot = ch & 1;
@@ -996,12 +1116,43 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         blp_outputs co_{ost, oit, oobj, ox, oy};
         blp_error e = blp_solve_batch(ch_h, &cb, &co_, s);
         if (e != BLP_SUCCESS) return fail(h, e, "piece %d: %s", ch, blp_last_error(ch_h));
-        // results back; x/y land at the caller's offsets
+        // results back; x/y of each LP land at the caller's offsets.  Only
+        // the piece's own LPs' ranges are copied (one copy per run of LPs
+        // whose ranges follow each other): with gapped or interleaved
+        // offsets the piece's device buffer holds nothing meaningful
+        // between them, and another piece may own those positions.
         HIP_TRY(h, hipMemcpyAsync(out->status + k0, ost, sizeof(int32_t) * Kc, hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipMemcpyAsync(out->iters + k0, oit, sizeof(int32_t) * Kc, hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipMemcpyAsync(out->obj + k0, oobj, sizeof(double) * Kc, hipMemcpyDeviceToHost, s));
-        if (nc) HIP_TRY(h, hipMemcpyAsync(out->x + rc.lo, ox, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-        if (nr) HIP_TRY(h, hipMemcpyAsync(out->y + rr.lo, oy, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<int64_t>& off = pass == 0 ? co : ro;
+            const std::vector<int32_t>& len = pass == 0 ? n : m;
+            const int64_t lo = pass == 0 ? rc.lo : rr.lo;
+            double* dst = pass == 0 ? out->x : out->y;
+            const double* src = pass == 0 ? ox : oy;
+            order.resize((size_t)Kc);
+            for (int64_t k = k0; k < k1; ++k) order[(size_t)(k - k0)] = k;
+            if (!std::is_sorted(order.begin(), order.end(),
+                                [&](int64_t a, int64_t b) { return off[a] < off[b]; }))
+                std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return off[a] < off[b]; });
+            int64_t run_lo = -1, run_hi = -1;
+            for (size_t q = 0; q <= order.size(); ++q) {
+                const bool last = q == order.size();
+                const int64_t k = last ? 0 : order[q];
+                if (!last && len[k] == 0) continue;
+                if (!last && off[k] == run_hi) {
+                    run_hi += len[k];
+                    continue;
+                }
+                if (run_hi > run_lo)
+                    HIP_TRY(h, hipMemcpyAsync(dst + run_lo, src + (run_lo - lo), sizeof(double) * (run_hi - run_lo),
+                                              hipMemcpyDeviceToHost, s));
+                if (!last) {
+                    run_lo = off[k];
+                    run_hi = off[k] + len[k];
+                }
+            }
+        }
     }
     for (int i = 0; i < 2; ++i) HIP_TRY(h, hipStreamSynchronize(h->pipe[i]));
     return BLP_SUCCESS;
@@ -1027,7 +1178,7 @@ blp_error blp_get_solution(blp_handle h, int64_t k, int32_t* status, double* obj
     if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
     if (k < 0 || k >= h->count) return fail(h, BLP_ERR_ARG, "k out of range");
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    HIP_TRY(h, wait_last(h));
     int m, n;
     int64_t ro, co;
     lp_offsets(h, k, &m, &n, &ro, &co);
@@ -1045,7 +1196,7 @@ blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, 
     if (!h) return BLP_ERR_ARG;
     if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    HIP_TRY(h, wait_last(h));
     const int64_t K = h->count;
     if (K == 0) return BLP_SUCCESS;
     int64_t tot_m = 0, tot_n = 0;
@@ -1078,6 +1229,7 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
     if (!g) return fail(h, BLP_ERR_ARG, "g is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, begin_call(h, s));
     KParams P = h->last;
     if (h->any_simplex && (dc || db || dA)) HIP_TRY(h, launch_backward_simplex(P, g, dc, db, dA, s));
     if (h->any_box && (dc || dl || du)) {
@@ -1085,6 +1237,7 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
         Q.bin = h->nreg + 1;
         HIP_TRY(h, launch_backward_hyperbox(Q, P.list ? h->n_box : h->count, g, dc, dl, du, s));
     }
+    HIP_TRY(h, end_call(h, s));
     return BLP_SUCCESS;
 }
 
@@ -1164,6 +1317,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
     if (!B || B->count <= 0 || sample <= 0) return fail(h, BLP_ERR_ARG, "autotune needs a non-empty batch and sample > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, begin_call(h, s));
     const int nreg = h->nreg, nbins = nreg + 2;
     // classify with the untuned table
     int saved[kMaxVariants];
@@ -1196,7 +1350,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         int32_t* tb = h->tune.as<int32_t>();
         int32_t hdr[3] = {0, S, 0};
         HIP_TRY(h, hipMemcpyAsync(tb, hdr, sizeof hdr, hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(tb + 4, h->list.as<int32_t>() + off[v], sizeof(int32_t) * S,
+        HIP_TRY(h, hipMemcpyAsync(tb + 4, sp.list + off[v], sizeof(int32_t) * S,
                                   hipMemcpyDeviceToDevice, s));
         KParams Q = sp.P;
         Q.list = tb + 4;
@@ -1238,6 +1392,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
     }
+    HIP_TRY(h, end_call(h, s));
     h->solved = false;  // the handle's outputs hold tuning runs, not a solve
     if (cache_path) return write_tuning(h, cache_path);
     return BLP_SUCCESS;
@@ -1252,7 +1407,7 @@ blp_error blp_last_kernel_ms(blp_handle h, double* ms, int32_t* n_entries) {
     if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
     if (!h->opt.profile || h->count == 0) return BLP_SUCCESS;
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    HIP_TRY(h, wait_last(h));
     for (int i = 0; i < n && i < (int)h->ev_used.size(); ++i) {
         if (!h->ev_used[i]) continue;
         float t = 0.f;
@@ -1269,7 +1424,7 @@ blp_error blp_last_bins(blp_handle h, int64_t* counts, int32_t* n_classes) {
     if (!counts) return BLP_SUCCESS;
     if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    HIP_TRY(h, wait_last(h));
     std::vector<int32_t> c(nbins, 0);
     if (h->last.list) {
         HIP_TRY(h, hipMemcpy(c.data(), h->last.bin_len, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost));

@@ -86,3 +86,31 @@ def crafted_batch(lps: list) -> lpgen.Batch:
             sense[ro:ro + mm] = d.get("sense", np.zeros(mm, np.int8))
     return lpgen.Batch(m, n, kind, a_off, row_off, col_off, A, b, sense, c, l, u,
                        np.arange(K, dtype=np.int64), np.where(kind == 1, 3, 1).astype(np.int32))
+
+
+def scattered_batch(seed: int = 17) -> lpgen.Batch:
+    """The mixed batch of the oracle's batch-driver pin: simplex and hyperbox
+    LPs with every outcome, stored in a permuted order at gapped offsets
+    (NaN in the gaps)."""
+    import pins
+    _, arrs, _ = pins._scattered_batch(seed)
+    K, m, n, kind, a_off, row_off, col_off, A, b, sense, c, l, u = arrs
+    return lpgen.Batch(m, n, kind, a_off, row_off, col_off, A, b, sense, c, l, u,
+                       np.arange(K, dtype=np.int64), np.where(kind == 1, 3, 1).astype(np.int32))
+
+
+def compare_scattered(hb: lpgen.Batch, g: dict, o: dict, tag: str = "") -> None:
+    """compare() for batches with gapped offsets: x and y only at the LPs'
+    own ranges (the gaps of the output buffers belong to nobody)."""
+    K = hb.count
+    xw = np.zeros(hb.c.shape[0], bool)
+    yw = np.zeros(max(1, hb.b.shape[0]), bool)
+    for k in range(K):
+        xw[hb.col_off[k]:hb.col_off[k] + hb.n[k]] = True
+        yw[hb.row_off[k]:hb.row_off[k] + hb.m[k]] = True
+    gg = dict(g)
+    oo = dict(o)
+    for d in (gg, oo):
+        d["x"] = np.where(xw, np.asarray(d["x"])[:xw.size], 0.0)
+        d["y"] = np.where(yw, np.asarray(d["y"])[:yw.size], 0.0)
+    compare(hb, gg, oo, strict=True, tag=tag)

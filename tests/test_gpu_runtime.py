@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import lpgen
-from solve_util import gpu_solve
+import oracle
+from solve_util import compare, compare_scattered, gpu_solve, scattered_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +22,7 @@ def test_graph_replay_matches_eager():
     import paper_1609_08114_amd as blp
     hb = lpgen.config(4, range(500, 620))
     ref = gpu_solve(hb)
+    compare(hb, ref, oracle.solve_batch(hb), strict=True, tag="eager")
     db = blp.DeviceBatch.from_host(hb)
     s = blp.Solver(graph=True)
     outs = []
@@ -36,12 +38,16 @@ def test_graph_replay_matches_eager():
     torch.cuda.synchronize()
     ref2 = gpu_solve(hb2)
     assert np.array_equal(_bits(out2["obj"][:100].cpu().numpy()), _bits(ref2["obj"]))
+    compare(hb2, ref2, oracle.solve_batch(hb2), strict=True, tag="cfg1")
     out3 = s.solve(db)
     torch.cuda.synchronize()
     outs.append({k: v.cpu().numpy().copy() for k, v in out3.items()})
     s.close()
     K = hb.count
-    for o in outs:
+    ora = oracle.solve_batch(hb)
+    for rep, o in enumerate(outs):
+        compare(hb, {k: (v[:K] if k in ("status", "iters", "obj") else v) for k, v in o.items()}, ora, strict=True,
+                tag=f"replay {rep}")
         assert np.array_equal(o["status"][:K], ref["status"])
         assert np.array_equal(_bits(o["obj"][:K]), _bits(ref["obj"]))
         assert np.array_equal(_bits(o["x"][:hb.c.size]), _bits(ref["x"][:hb.c.size]))
@@ -69,6 +75,10 @@ def test_autotune_remap_and_cache(tmp_path):
     K = hb.count
     assert np.array_equal(out["status"][:K].cpu().numpy(), ref["status"])
     assert np.array_equal(_bits(out["obj"][:K].cpu().numpy()), _bits(ref["obj"]))
+    tuned = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("status", "iters", "obj"):
+        tuned[k] = tuned[k][:K]
+    compare(hb, tuned, oracle.solve_batch(hb), strict=True, tag="autotuned")
     s.close()
     s2 = blp.Solver()
     blp.blp_load_tuning(s2.h, path)
@@ -158,15 +168,60 @@ def test_rpc_rule_reaches_the_same_optimum():
     compare(hb, gpu_solve(hb, pivot_rule=blp.BLP_RULE_RPC, seed=5), oracle_solve(hb), strict=False, tag="rpc-small")
 
 
+def _host_solve(hb, chunks, fill=0.0):
+    import ctypes
+
+    import paper_1609_08114_amd as blp
+    s = blp.Solver()
+    K = hb.count
+    st = np.zeros(K, np.int32)
+    it = np.zeros(K, np.int32)
+    ob = np.zeros(K)
+    x = np.full(hb.c.size, fill)
+    y = np.full(max(1, hb.b.size), fill)
+    keep = [np.ascontiguousarray(a) for a in (hb.m, hb.n, hb.kind, hb.a_off, hb.row_off, hb.col_off)]
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    b = blp.blp_batch(K, 0, 0, *[P(a) for a in keep], P(hb.A), P(hb.b), P(hb.sense), P(hb.c), P(hb.l), P(hb.u))
+    o = blp.blp_outputs(P(st), P(it), P(ob), P(x), P(y))
+    try:
+        blp.blp_solve_batch_host(s.h, b, o, chunks)
+    finally:
+        s.close()
+    return {"status": st, "iters": it, "obj": ob, "x": x, "y": y}
+
+
+@pytest.mark.parametrize("chunks", [1, 3, 7])
+def test_host_resident_scattered_offsets(chunks):
+    """Host-resident pieces with permuted, gapped offsets (pieces' ranges
+    interleave): every LP's results at its own offsets, as the oracle solves
+    them, and the gaps of the output arrays untouched."""
+    hb = scattered_batch()
+    SENT = 1234.5
+    g = _host_solve(hb, chunks, fill=SENT)
+    compare_scattered(hb, g, oracle.solve_batch(hb), tag=f"host-scattered-{chunks}")
+    xw = np.zeros(hb.c.size, bool)
+    yw = np.zeros(hb.b.size, bool)
+    for k in range(hb.count):
+        xw[hb.col_off[k]:hb.col_off[k] + hb.n[k]] = True
+        yw[hb.row_off[k]:hb.row_off[k] + hb.m[k]] = True
+    assert (g["x"][~xw] == SENT).all() and (g["y"][:hb.b.size][~yw] == SENT).all()
+
+
+def test_device_scattered_offsets():
+    hb = scattered_batch()
+    compare_scattered(hb, gpu_solve(hb), oracle.solve_batch(hb), tag="device-scattered")
+
+
 @pytest.mark.parametrize("chunks", [1, 3, 0])
 def test_host_resident_pipeline(chunks):
-    """Host arrays in, host results out, pieces on two streams: identical to
-    the device-resident solve."""
+    """Host arrays in, host results out, pieces on two streams: as the oracle
+    solves the batch, and identical to the device-resident solve."""
     import ctypes
 
     import paper_1609_08114_amd as blp
     hb = lpgen.config(4, range(4000, 4150))
     ref = gpu_solve(hb)
+    compare(hb, _host_solve(hb, chunks), oracle.solve_batch(hb), strict=True, tag=f"host-{chunks}")
     s = blp.Solver()
     K = hb.count
     st = np.zeros(K, np.int32)
@@ -194,6 +249,7 @@ def test_row_major_workspace_identical():
     hb = lpgen.config(4, range(5000, 5060))
     a = gpu_solve(hb, variant=-2)
     b = gpu_solve(hb, variant=-2, layout=blp.BLP_LAYOUT_ROW)
+    compare(hb, b, oracle.solve_batch(hb), strict=True, tag="row-major")
     for k in ("status", "iters"):
         assert np.array_equal(a[k], b[k])
     for k in ("obj", "x", "y"):
@@ -227,3 +283,36 @@ def test_mixed_batch_classes_run_concurrently():
             assert np.array_equal(_bits(out["x"][:hb.c.size].cpu().numpy()), _bits(g["x"][:hb.c.size]))
     finally:
         s.close()
+
+
+def test_one_handle_on_two_streams():
+    """A handle's calls reuse its buffers: a solve issued on a second stream
+    right after one on a first stream waits for it, so both results are the
+    oracle's."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    h1 = lpgen.config(5, range(300), part="simplex")
+    h2 = lpgen.config(4, range(300, 420))
+    d1, d2 = blp.DeviceBatch.from_host(h1), blp.DeviceBatch.from_host(h2)
+    s = blp.Solver()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        o1 = s.solve(d1, stream=sa)
+        o2 = s.solve(d2, stream=sb)  # own buffers of the handle reused at once
+        g = torch.ones(h2.count, dtype=torch.float64, device="cuda")
+        grads = s.backward(g, stream=sa, want=("dc",))
+        torch.cuda.synchronize()
+        r1 = {k: v.cpu().numpy() for k, v in o1.items()}
+        r2 = {k: v.cpu().numpy() for k, v in o2.items()}
+        dc = grads["dc"].cpu().numpy()
+    finally:
+        s.close()
+    for hb, r, tag in ((h1, r1, "first"), (h2, r2, "second")):
+        for k in ("status", "iters", "obj"):
+            r[k] = r[k][:hb.count]
+        compare(hb, r, oracle.solve_batch(hb), strict=True, tag=tag)
+    ok = r2["status"] == 0
+    for k in np.nonzero(ok)[0][:50]:
+        co, n = h2.col_off[k], h2.n[k]
+        assert np.array_equal(_bits(dc[co:co + n]), _bits(r2["x"][co:co + n])) or h2.kind[k] == 1
