@@ -45,13 +45,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_solver(blp, torch, db, steps, warmup, profile=True, warm_ms=0.0, **kw):
+def time_solver(blp, torch, db, steps, warmup, profile=True, warm_ms=0.0, step_times=None, kernel_avg=False,
+                **kw):
     """Warm up (`warmup` solves, and with `warm_ms` > 0 at least that much wall
     time, synchronising after 1, 2, 4, ... up to 16 solves), then time `steps` solves enqueued
     back to back on one stream (one synchronisation at each end); returns (ms
     per step, per-class kernel ms of the last timed step from the HIP events
     the library records around each kernel class (zeros without `profile`),
-    last outputs, bins)."""
+    last outputs, bins).  With `step_times` (a list), HIP events recorded on
+    the stream between the back-to-back steps add each step's device time to
+    it.  With `kernel_avg`, a second loop of `steps` profiled solves (each read
+    back) replaces the per-class kernel ms by their average over those steps."""
     s = blp.Solver(profile=profile, **kw)
     stream = torch.cuda.Stream()
     out = None  # output tensors: allocated by the first solve, reused by every later one
@@ -65,12 +69,25 @@ def time_solver(blp, torch, db, steps, warmup, profile=True, warm_ms=0.0, **kw):
             torch.cuda.synchronize()
             n = min(16, 2 * n)
     torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if step_times is not None else None
     t0 = time.perf_counter()
-    for _ in range(steps):
+    if evs:
+        evs[0].record(stream)
+    for i in range(steps):
         out = s.solve(db, stream=stream, outputs=out)
+        if evs:
+            evs[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if evs:
+        step_times.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     kms = blp.blp_last_kernel_ms(s.h)
+    if kernel_avg and profile:
+        acc = np.zeros_like(kms)
+        for _ in range(steps):
+            out = s.solve(db, stream=stream, outputs=out)
+            acc += blp.blp_last_kernel_ms(s.h)
+        kms = acc / steps
     bins = blp.blp_last_bins(s.h)
     s.close()
     return (t1 - t0) * 1e3 / steps, kms, out, bins
@@ -89,7 +106,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=50_000)
-    ap.add_argument("--one-per-launch-sample", type=int, default=2_000)
+    ap.add_argument("--one-per-launch-sample", type=int, default=50_000)
     ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -129,7 +146,8 @@ def main():
     db = blp.DeviceBatch.from_host(hb)
     torch.cuda.synchronize()
     log("timing persistent mode")
-    ms, kms, out, bins = time_solver(blp, torch, db, args.steps, args.warmup)
+    step_ms = []
+    ms, kms, out, bins = time_solver(blp, torch, db, args.steps, args.warmup, step_times=step_ms, kernel_avg=True)
     status = out["status"][:K].cpu().numpy()
     iters = out["iters"][:K].cpu().numpy().astype(np.int64)
     obj = out["obj"][:K].cpu().numpy()
@@ -141,13 +159,14 @@ def main():
     dom = int(np.argmax(kms))
     dom_ms = float(kms[dom])
     m = n = 100
-    # Work per pivot as the method states it: the full tableau of a type-1
-    # LP has (m + 1) rows and (n + m + 1) columns, one FMA per entry.  The
-    # kernel holds only the n nonbasic columns and the rhs (the basic
-    # columns are unit vectors), so it executes (m + 1)(n + 1) of them.
-    flops = float(iters.sum()) * 2.0 * (m + 1) * (n + m + 1)
+    # Work per pivot as executed: the kernel stores the condensed tableau,
+    # the n nonbasic columns and the rhs of the m constraint rows and the
+    # objective row, (m + 1)(n + 1) entries, one FMA each (the basic columns
+    # of the full tableau of Sec. 3.1 are unit vectors and are not stored).
+    # The full tableau, (m + 1)(n + m + 1) entries, is reported as context.
     executed = float(iters.sum()) * 2.0 * (m + 1) * (n + 1)
-    achieved = flops / (dom_ms / 1e3) / 1e12
+    full = float(iters.sum()) * 2.0 * (m + 1) * (n + m + 1)
+    achieved = executed / (dom_ms / 1e3) / 1e12
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tf = json.load(open(TRAFFIC_FILE))
@@ -157,22 +176,17 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "kernel": names[dom], "kernel_ms": round(dom_ms, 4),
-                "algorithmic_flops": flops, "executed_flops": executed,
-                "executed_frac": round(executed / (dom_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
-                "pivots": int(iters.sum()),
-                # the same update priced as a tableau resident in LDS (read and
-                # write 8 bytes per full-tableau entry per pivot): the bound an
-                # LDS-staged kernel could not exceed; this kernel keeps the
-                # tableau in registers instead
-                "lds_model_GBps": round(flops * 8.0 / (dom_ms / 1e3) / 1e9, 1),
-                "lds_model_frac": round(flops * 8.0 / (dom_ms / 1e3) / 1e9 / PEAK_LDS_GBS, 4),
+                "kernel_ms_note": f"mean of {args.steps} profiled solves (HIP events on the solve's stream)",
+                "flops_per_pivot": 2 * (m + 1) * (n + 1), "pivots": int(iters.sum()), "executed_flops": executed,
+                "context_full_tableau_flops": full,
+                "context_full_tableau_frac": round(full / (dom_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
                 "hbm_input_bytes": input_bytes,
                 "hbm_frac_of_input_read": round(input_bytes / (dom_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 
     # ------------------------------------------------- one LP per launch
     S = min(args.one_per_launch_sample, K)
     log(f"one-LP-per-launch on the first {S} LPs")
-    sub = blp.DeviceBatch.from_host(lpgen.config(2, range(S)))
+    sub = db if S == K else blp.DeviceBatch.from_host(lpgen.config(2, range(S)))
     ms1, _, out1, _ = time_solver(blp, torch, sub, 1, 1, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
     rate1 = S / (ms1 / 1e3)
     assert np.array_equal(out1["obj"][:S].cpu().numpy().view(np.int64), obj[:S].view(np.int64))
@@ -241,7 +255,11 @@ def main():
                                "A~U(1,10) b~U(10,100) c~U(1,10), seed 1002",
                    "batch": K, "m": 100, "n": 100, "mode": "persistent"},
         "end_to_end_pinned_host": host,
-        "one_per_launch": {"value": round(rate1, 1), "unit": "LPs/s", "sample": f"first {S} LPs",
+        "step_ms": {"mean": round(float(np.mean(step_ms)), 4), "median": round(float(np.median(step_ms)), 4),
+                    "min": round(float(np.min(step_ms)), 4), "max": round(float(np.max(step_ms)), 4),
+                    "runs": len(step_ms), "note": "device time of each timed step (HIP events between steps)"},
+        "one_per_launch": {"value": round(rate1, 1), "unit": "LPs/s",
+                           "sample": "all LPs" if S == K else f"first {S} LPs",
                            "speedup_persistent": round(value / rate1, 2)},
         "statuses": np.bincount(status, minlength=5).tolist(),
         "pivots_per_lp": round(float(iters.mean()), 3),
@@ -445,75 +463,155 @@ def layout_ablation(blp, torch, lpgen, K=512) -> dict:
     return res
 
 
-def bench_classes(blp, torch, lpgen) -> dict:
-    """LPs/s of the other workload shapes, persistent vs one per launch, on
-    bounded samples (named in each entry)."""
+def _stats(ts) -> dict:
+    return {"mean_ms": round(float(np.mean(ts)), 4), "median_ms": round(float(np.median(ts)), 4),
+            "min_ms": round(float(np.min(ts)), 4), "max_ms": round(float(np.max(ts)), 4), "runs": len(ts)}
+
+
+# Workloads at their stated sizes: (name, config, part, LPs, one-LP-per-launch
+# LPs (None: all of them), timed runs)
+CLASS_PLAN = [
+    ("type1_5x5", 1, None, 1_000, None, 10),
+    ("type1_20..150", 5, "simplex", 20_000, None, 10),
+    ("type2_200x200", 3, None, 10_000, 50, 10),
+    ("mixed_5..300", 4, None, 200_000, 200, 5),
+    ("hyperbox_n5", 5, "box5", 4_000_000, 0, 10),
+    ("hyperbox_n28", 5, "box28", 6_000_000, 0, 10),
+]
+
+
+def bench_classes(blp, torch, lpgen, plan=None) -> dict:
+    """Every workload at its stated size: persistent LPs/s (mean and median
+    of the timed runs' device times, HIP events between back-to-back runs),
+    the kernel classes it used, one-LP-per-launch on all of its LPs or on a
+    stated leading subset, and for the mixed batch the autotuned rate; for
+    workload 5 also the backward pass (LPs/s, bytes and HBM fraction)."""
     res = {}
-    plan = [
-        ("type1_5x5", 1, None, 1000, 1000),
-        ("type2_200x200", 3, None, 1000, 50),
-        ("mixed_5..300", 4, None, 4000, 200),
-        ("hyperbox_n5", 5, "box5", 1_000_000, 0),
-        ("hyperbox_n28", 5, "box28", 1_000_000, 0),
-        ("type1_20..150", 5, "simplex", 4000, 200),
-    ]
-    for name, cfg, part, n_batch, n_single in plan:
-        log(f"class {name}: {n_batch} LPs")
+    names = [v[0] for v in blp.variants()] + ["streaming", "hyperbox", "binning"]
+    for name, cfg, part, n_batch, n_single, runs in (plan or CLASS_PLAN):
+        log(f"class {name}: generating {n_batch} LPs")
+        t0 = time.perf_counter()
         hb = lpgen.config(cfg, range(n_batch), part=part) if part else lpgen.config(cfg, range(n_batch))
+        log(f"class {name}: generated in {time.perf_counter() - t0:.1f} s; copying to HBM")
         db = blp.DeviceBatch.from_host(hb)
-        # short classes: enough warm-up and timed steps to cover tens of ms
-        # (3 steps of < 1 ms right after the CPU-only input generation
-        # measured the GPU's ramp-up, not the solve: the warm-up also runs
-        # for at least 100 ms of wall time)
-        # (steps timed without the per-class profiling events, which add
-        # their own packets to every launch; kernel times from one profiled
-        # solve)
-        ms1, kms, _, _ = time_solver(blp, torch, db, 1, 1)
-        # (at most 64 steps in flight: with a few hundred small solves
-        # enqueued back to back the HIP runtime's enqueue itself stalls)
-        steps = max(3, min(64, int(np.ceil(40.0 / max(ms1, 1e-3)))))
+        # kernel classes and their device times from one profiled solve
+        ms1, kms, _, bins = time_solver(blp, torch, db, 1, 1)
+        log(f"class {name}: one profiled solve {ms1:.2f} ms")
+        # short classes: warm-up of at least 100 ms of wall time, then the
+        # timed runs back to back (no profiling events)
         warm = max(1, min(32, int(np.ceil(20.0 / max(ms1, 1e-3)))))
-        ms, _, out, _ = time_solver(blp, torch, db, steps, warm, profile=False, warm_ms=100.0)
-        entry_steps = steps
+        ts = []
+        ms, _, out, _ = time_solver(blp, torch, db, runs, warm if ms1 < 100 else 0, profile=False,
+                                    warm_ms=100.0 if ms1 < 100 else 0.0, step_times=ts)
         st = np.bincount(out["status"][:n_batch].cpu().numpy(), minlength=5).tolist()
-        entry = {"lps": n_batch, "persistent_lps_per_s": round(n_batch / (ms / 1e3), 1), "ms": round(ms, 3),
-                 "timed_steps": entry_steps, "statuses": st}
+        med = float(np.median(ts))
+        entry = {"lps": n_batch, "persistent_lps_per_s": round(n_batch / (med / 1e3), 1),
+                 "persistent_lps_per_s_mean": round(n_batch / (float(np.mean(ts)) / 1e3), 1),
+                 "wall_ms_per_run": round(ms, 3), "device_ms": _stats(ts), "statuses": st,
+                 "bins": {names[i]: int(bins[i]) for i in range(len(bins)) if bins[i]},
+                 "kernel_ms": {names[i]: round(float(kms[i]), 4) for i in range(len(kms)) if kms[i] > 0}}
         if part and part.startswith("box"):
-            # Eq. (7) is a stream: read c, l, u, write x, obj, status, iters
+            # Eq. (7) streams c, l, u in and x, obj, status, iters out
             n = int(hb.n[0])
-            kb = float(kms[-2])
+            kb = float(kms[len(blp.variants()) + 1])
             byt = n_batch * (24.0 * n + 8.0 * n + 16.0)
-            entry.update({"kernel_ms": round(kb, 4), "hbm_bytes": byt, "hbm_GBps": round(byt / kb / 1e6, 1),
-                          "hbm_frac": round(byt / kb / 1e6 / PEAK_HBM_GBS, 4)})
-        if name == "type2_200x200":
-            # the streaming kernel rewrites the condensed tableau every pivot:
-            # 16 B per cell of ldk rows x (n + n_art + 1) columns in phase 1,
-            # fewer in phase 2 (artificial columns skipped), so this is an
-            # upper bound; the algorithmic figure is the full tableau of
-            # Sec. 3.1 ((m + 2) x (n + m + n_art + 1)) at every pivot
+            entry.update({"kernel_ms": round(kb, 4), "algorithmic_bytes": byt, "GBps": round(byt / kb / 1e6, 1),
+                          "hbm_frac": round(byt / kb / 1e6 / PEAK_HBM_GBS, 4),
+                          "note": "batch larger than the 256 MB last-level cache; bytes are the algorithmic "
+                                  "stream (HBM counters of the same kernels in profiles/)"})
+        if cfg == 3:
+            # the streaming kernel reads and writes each stored tableau entry
+            # once per pivot (ldk x (n + n_art + 1) in phase 1, the artificial
+            # columns skipped in phase 2); part of it hits the L2 and the
+            # last-level cache, so this is a tableau stream, not HBM traffic
             m, n = int(hb.m[0]), int(hb.n[0])
             sense = hb.sense.reshape(n_batch, m) != 0
             b = hb.b.reshape(n_batch, m)
             nart = ((np.where(sense, -b, b)) < 0).sum(axis=1)
             it = out["iters"][:n_batch].cpu().numpy().astype(np.float64)
-            ldk = ((m + 2 + 15) // 16) * 16
             gms = float(kms[len(blp.variants())])
-            upper = float((it * 16.0 * ldk * (n + nart + 1)).sum())
-            alg = float((it * 16.0 * (m + 2) * (n + m + nart + 1)).sum())
+            stored = float((it * 16.0 * (m + 2) * (n + nart + 1)).sum())
             entry.update({"streaming_kernel_ms": round(gms, 3), "pivots_per_lp": round(float(it.mean()), 1),
-                          "streamed_GBps_upper": round(upper / gms / 1e6, 1),
-                          "streamed_hbm_frac_upper": round(upper / gms / 1e6 / PEAK_HBM_GBS, 4),
-                          "algorithmic_full_tableau_GBps": round(alg / gms / 1e6, 1)})
-        if n_single:
-            sub = lpgen.config(cfg, range(n_single), part=part) if part else lpgen.config(cfg, range(n_single))
-            sdb = blp.DeviceBatch.from_host(sub)
-            ms1, _, _, _ = time_solver(blp, torch, sdb, 1, 0, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
-            entry["one_per_launch_lps_per_s"] = round(n_single / (ms1 / 1e3), 1)
-            entry["one_per_launch_sample"] = n_single
+                          "tableau_stream_GBps_l2_mall_hbm": round(stored / gms / 1e6, 1),
+                          "tableau_stream_note": "16 B per stored entry per pivot (phase-1 width, an upper "
+                                                 "bound); served by L2, the last-level cache and HBM"})
+        if n_single is None or n_single > 0:
+            S = n_batch if n_single is None else n_single
+            sub = db if S == n_batch else blp.DeviceBatch.from_host(
+                lpgen.config(cfg, range(S), part=part) if part else lpgen.config(cfg, range(S)))
+            log(f"class {name}: one LP per launch on {S} LPs")
+            ms1, _, _, _ = time_solver(blp, torch, sub, 1, 0, mode=blp.BLP_MODE_ONE_PER_LAUNCH)
+            entry["one_per_launch_lps_per_s"] = round(S / (ms1 / 1e3), 1)
+            entry["one_per_launch_sample"] = "all LPs" if S == n_batch else f"first {S} LPs"
             entry["speedup"] = round(entry["persistent_lps_per_s"] / entry["one_per_launch_lps_per_s"], 2)
+            del sub
+        if cfg == 4:
+            entry["autotuned"] = autotune_gain(blp, torch, db, n_batch, med)
+        if cfg == 5:
+            entry["backward"] = bench_backward(blp, torch, lpgen, hb, db, part)
         res[name] = entry
-        log(f"  {entry}")
+        log(f"  {name}: {entry}")
+        del db, hb, out
+        torch.cuda.empty_cache()
     return res
+
+
+def autotune_gain(blp, torch, db, K, base_ms, sample=256, runs=3) -> dict:
+    """The autotuner on the batch itself (a calibration sample per size bin,
+    every variant able to hold the bin), then the tuned solve timed."""
+    s = blp.Solver()
+    t0 = time.perf_counter()
+    s.autotune(db, sample=sample)
+    tune_s = time.perf_counter() - t0
+    remap = blp.blp_tuning(s.h)
+    s.close()
+    names = [v[0] for v in blp.variants()] + ["streaming"]
+    changed = {names[v]: names[w] for v, w in enumerate(remap) if w != v}
+    # a tuned handle: load the remap through a cache file
+    import tempfile
+    s = blp.Solver()
+    path = os.path.join(tempfile.mkdtemp(), "tune.json")
+    s.autotune(db, sample=sample, cache_path=path)
+    s.close()
+    ts = []
+    ms, _, out, _ = time_solver(blp, torch, db, runs, 0, profile=False, step_times=ts, tune_cache=path)
+    med = float(np.median(ts))
+    return {"sample_per_bin": sample, "tuning_s": round(tune_s, 2), "remap": changed,
+            "device_ms": _stats(ts), "lps_per_s": round(K / (med / 1e3), 1),
+            "gain_vs_untuned": round(base_ms / med, 3)}
+
+
+def bench_backward(blp, torch, lpgen, hb, db, part, runs=10) -> dict:
+    """blp_backward after a solve of the batch: loss = sum w_k opt_k with
+    w ~ U(0, 1); LPs/s and the algorithmic HBM bytes (simplex: read status,
+    g, x, y, write dc, db, dA; hyperbox: read status, g, c, x, write dc, dl,
+    du)."""
+    K = hb.count
+    s = blp.Solver()
+    out = s.solve(db)
+    w = torch.from_numpy(lpgen.weights(lpgen.SEEDS[5] + 100, np.arange(K))).to("cuda")
+    grads = s.backward(w)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(runs + 1)]
+    evs[0].record(stream)
+    for i in range(runs):
+        grads = s.backward(w)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ts = [evs[i].elapsed_time(evs[i + 1]) for i in range(runs)]
+    s.close()
+    m = hb.m.astype(np.float64)
+    n = hb.n.astype(np.float64)
+    if part == "simplex":
+        byt = float((12.0 + 8.0 * (m + n) + 8.0 * (m * n + m + n)).sum())
+    else:
+        byt = float((12.0 + 16.0 * n + 24.0 * n).sum())
+    med = float(np.median(ts))
+    # (the gradient buffers are allocated once by Solver.backward before the
+    # timed runs and rewritten by each)
+    return {"lps": K, "device_ms": _stats(ts), "lps_per_s": round(K / (med / 1e3), 1), "algorithmic_bytes": byt,
+            "GBps": round(byt / med / 1e6, 1), "hbm_frac": round(byt / med / 1e6 / PEAK_HBM_GBS, 4)}
 
 
 if __name__ == "__main__":

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BLP_ABI_VERSION 1
+#define BLP_ABI_VERSION 2
 
 typedef struct blp_handle_s* blp_handle;
 
@@ -100,6 +100,16 @@ typedef struct {
                               tableau: the non-coalesced access of Sec. 4.3's comparison).  Results are
                               bit-identical; only speed differs */
     uint64_t seed;         /* RPC only: Philox4x32-10 key; draw = (seed, LP index, pivot count) */
+    uint64_t mem_limit;    /* 0: no limit.  Otherwise the bytes of device memory blp_solve_batch may
+                              hold for one call: its own result buffers (for outputs passed as NULL),
+                              the batch metadata and work lists, and the streaming kernel's
+                              workspace.  A batch needing more is solved in consecutive chunks of
+                              LPs, each the largest that fits (the batch capacity N = S / Y of
+                              Sec. 4.5, Eq. (5), with S the limit and Y the bytes per LP); results
+                              are identical.  BLP_ERR_NOMEM if the result buffers or a single LP do
+                              not fit. */
+    const char* tune_cache;/* NULL, or a file written by blp_autotune: blp_create loads it (same as
+                              blp_load_tuning) and fails with its error if it cannot */
 } blp_options;
 
 /* Workspace layouts of the streaming kernel (Sec. 4.3). */
@@ -119,7 +129,9 @@ enum { BLP_RULE_LPC = 0, BLP_RULE_RPC = 1 };
  *   sense  int8,    length m at sense + row_off[k] (BLP_LE / BLP_GE)
  *   c      float64, length n at c + col_off[k]
  *   l, u   float64, length n at l/u + col_off[k] (hyperbox LPs only; may be
- *          NULL when the batch has none)
+ *          NULL when the batch has none); with shared_box nonzero, one box
+ *          of length n at l and u serves every hyperbox LP (all of them must
+ *          then have the same n; the many-objectives use of Sec. 6)
  * If `uniform` is nonzero, every LP has m[0], n[0], kind[0] and the offsets
  * are the packed ones (a_off = k m n, row_off = k m, col_off = k n); the
  * offset arrays are then ignored.  Otherwise offsets may be NULL, meaning
@@ -127,7 +139,7 @@ enum { BLP_RULE_LPC = 0, BLP_RULE_RPC = 1 };
 typedef struct {
     int64_t count;
     int32_t uniform;
-    int32_t reserved_;
+    int32_t shared_box;  /* nonzero: the hyperbox LPs share one box (see above) */
     const int32_t* m;
     const int32_t* n;
     const int32_t* kind;
@@ -217,18 +229,24 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
 blp_error blp_get_solution(blp_handle h, int64_t k, int32_t* status, double* obj, double* x, double* y,
                            int32_t* iters);
 
-/* Copy all results of the last solve to HOST memory, packed like the
- * outputs (synchronises).  Any pointer may be NULL. */
+/* Copy all results of the last solve, packed like the outputs: with
+ * on_device == 0 to HOST memory (synchronises); otherwise to DEVICE memory,
+ * ordered on the last solve's stream (returns at once).  Any pointer may be
+ * NULL. */
 blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, double* obj, double* x,
-                                 double* y);
+                                 double* y, int32_t on_device);
 
 /* Adjoint of the last solve for loss = sum_k g[k] obj_k (an extension beyond
  * the paper; valid at non-degenerate optima where x* and y* are unique).
  * All pointers are DEVICE memory, packed like the batch; any output may be
  * NULL to skip it.  Simplex LP k:  dc = g_k x*,  db = g_k y*,
  * dA = -g_k y* x*^T (row-major at a_off[k]).  Hyperbox LP k:  dc = g_k h,
- * dl_i = g_k min(c_i, 0),  du_i = g_k max(c_i, 0).  LPs whose status is not
- * BLP_OPTIMAL get zero gradients. */
+ * dl_i = g_k min(c_i, 0),  du_i = g_k max(c_i, 0); with a shared box, dl and
+ * du have length n and hold the sums of those terms over the hyperbox LPs,
+ * added in a fixed order (blocks of 1,024 consecutive LPs, each reduced by a
+ * fixed tree, then the block sums in block order), so repeated calls give
+ * the same bits.  LPs whose status is not BLP_OPTIMAL get zero gradients.
+ * After a solve that mem_limit split into chunks: BLP_ERR_STATE. */
 blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, double* dA, double* dl,
                        double* du, void* hip_stream);
 

@@ -38,11 +38,12 @@ class blp_options(ctypes.Structure):
                 ("bland_after", ctypes.c_int32), ("eps_price", ctypes.c_double), ("eps_piv", ctypes.c_double),
                 ("eps_feas", ctypes.c_double), ("variant", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("graph", ctypes.c_int32), ("pivot_rule", ctypes.c_int32),
-                ("layout", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("layout", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mem_limit", ctypes.c_uint64),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class blp_batch(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int64), ("uniform", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+    _fields_ = [("count", ctypes.c_int64), ("uniform", ctypes.c_int32), ("shared_box", ctypes.c_int32),
                 ("m", ctypes.c_void_p), ("n", ctypes.c_void_p), ("kind", ctypes.c_void_p),
                 ("a_off", ctypes.c_void_p), ("row_off", ctypes.c_void_p), ("col_off", ctypes.c_void_p),
                 ("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("sense", ctypes.c_void_p),
@@ -82,7 +83,7 @@ def lib() -> ctypes.CDLL:
         L.blp_last_error.restype = ctypes.c_char_p
         L.blp_solve_batch.argtypes = [vp, P(blp_batch), P(blp_outputs), vp]
         L.blp_get_solution.argtypes = [vp, i64, vp, vp, vp, vp, vp]
-        L.blp_get_solution_batch.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.blp_get_solution_batch.argtypes = [vp, vp, vp, vp, vp, vp, i32]
         L.blp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.blp_last_bins.argtypes = [vp, vp, P(i32)]
         L.blp_variant_info.argtypes = [i32, ctypes.c_char_p, i32, P(i32), P(i32)]
@@ -144,8 +145,8 @@ def blp_get_solution(h, k: int, status=None, obj=None, x=None, y=None, iters=Non
     _check(h, lib().blp_get_solution(h, k, status, obj, x, y, iters))
 
 
-def blp_get_solution_batch(h, status=None, iters=None, obj=None, x=None, y=None) -> None:
-    _check(h, lib().blp_get_solution_batch(h, status, iters, obj, x, y))
+def blp_get_solution_batch(h, status=None, iters=None, obj=None, x=None, y=None, on_device: int = 0) -> None:
+    _check(h, lib().blp_get_solution_batch(h, status, iters, obj, x, y, on_device))
 
 
 def blp_backward(h, g, dc=None, db=None, dA=None, dl=None, du=None, stream: int | None = None) -> None:
@@ -234,13 +235,16 @@ class DeviceBatch:
     l: object
     u: object
     uniform: bool
+    shared_box: bool = False  # l and u: one box of length n for every hyperbox LP
 
     @property
     def count(self) -> int:
         return int(self.m.shape[0]) if not self.uniform else self._count
 
     @classmethod
-    def from_host(cls, hb, device="cuda", uniform: bool | None = None) -> "DeviceBatch":
+    def from_host(cls, hb, device="cuda", uniform: bool | None = None, shared_box: bool = False) -> "DeviceBatch":
+        """Copy a packed host batch to the device.  With `shared_box`, hb.l
+        and hb.u hold the one box (length n) of every hyperbox LP."""
         import torch
         uni = hb.uniform if uniform is None else uniform
 
@@ -254,7 +258,7 @@ class DeviceBatch:
                  sense=dev(hb.sense if hb.sense.size else np.zeros(1, np.int8), torch.int8),
                  c=dev(hb.c, torch.float64),
                  l=dev(hb.l, torch.float64) if has_box else None,
-                 u=dev(hb.u, torch.float64) if has_box else None, uniform=uni)
+                 u=dev(hb.u, torch.float64) if has_box else None, uniform=uni, shared_box=shared_box)
         db._count = hb.count
         return db
 
@@ -263,7 +267,7 @@ class DeviceBatch:
         self._keep = [np.ascontiguousarray(a) for a in (self.m, self.n, self.kind, self.a_off, self.row_off,
                                                        self.col_off)]
         m, n, kind, ao, ro, co = [a.ctypes.data_as(ctypes.c_void_p) for a in self._keep]
-        return blp_batch(K, 1 if self.uniform else 0, 0, m, n, kind,
+        return blp_batch(K, 1 if self.uniform else 0, 1 if self.shared_box else 0, m, n, kind,
                          None if self.uniform else ao, None if self.uniform else ro, None if self.uniform else co,
                          _ptr(self.A), _ptr(self.b), _ptr(self.sense), _ptr(self.c), _ptr(self.l), _ptr(self.u))
 
@@ -273,12 +277,15 @@ class Solver:
 
     def __init__(self, device: int = 0, mode: int = BLP_MODE_PERSISTENT, variant: int = -1, max_iter: int = 0,
                  workers_per_cu: int = 0, bland_after: int = 0, profile: bool = False, graph: bool = False,
-                 pivot_rule: int = BLP_RULE_LPC, seed: int = 0, layout: int = BLP_LAYOUT_COLUMN):
+                 pivot_rule: int = BLP_RULE_LPC, seed: int = 0, layout: int = BLP_LAYOUT_COLUMN,
+                 mem_limit: int = 0, tune_cache: str | None = None):
         o = blp_options_default()
         o.device, o.mode, o.variant, o.max_iter = device, mode, variant, max_iter
         o.workers_per_cu, o.bland_after, o.profile = workers_per_cu, bland_after, 1 if profile else 0
         o.graph = 1 if graph else 0
         o.pivot_rule, o.seed, o.layout = pivot_rule, seed, layout
+        o.mem_limit = mem_limit
+        o.tune_cache = tune_cache.encode() if tune_cache else None
         self.device = device
         self.h = blp_create(o)
 
@@ -338,14 +345,21 @@ class Solver:
         self._tune_batch = db.c_struct()
         blp_autotune(self.h, self._tune_batch, sample, cache_path, st.cuda_stream)
 
-    def backward(self, g, stream=None, want=("dc", "db", "dA", "dl", "du")) -> dict:
+    def backward(self, g, stream=None, want=("dc", "db", "dA", "dl", "du"), out: dict | None = None) -> dict:
+        """Gradients of sum_k g[k] obj_k into new tensors (or into `out`,
+        the dict a previous call returned: nothing is allocated then)."""
         import torch
         db, _ = self._last
         dev = g.device
-        res = {}
-        for k in want:
-            src = {"dc": db.c, "db": db.b, "dA": db.A, "dl": db.l, "du": db.u}[k]
-            res[k] = None if src is None else torch.zeros_like(src)
+        if out is not None:
+            res = out
+        else:
+            res = {}
+            for k in want:
+                src = {"dc": db.c, "db": db.b, "dA": db.A, "dl": db.l, "du": db.u}[k]
+                if k in ("dl", "du") and src is not None and getattr(db, "shared_box", False):
+                    src = src[:int(db.n[db.kind == 1][0])]
+                res[k] = None if src is None else torch.zeros_like(src)
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         blp_backward(self.h, _ptr(g), _ptr(res.get("dc")), _ptr(res.get("db")), _ptr(res.get("dA")),
                      _ptr(res.get("dl")), _ptr(res.get("du")), st.cuda_stream)

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblp.so")
 SOURCES = ["simplex_reg.hip", "simplex_gm.hip", "aux_kernels.hip", "blp_runtime.cpp"]
-HEADERS = ["blp_kernels.hpp", "simplex_common.hpp", "simplex_blk.hpp", "variants.hpp", "aux_kernels.hpp"]
+HEADERS = ["blp_kernels.hpp", "simplex_common.hpp", "simplex_blk.hpp", "simplex_lane.hpp", "variants.hpp",
+           "aux_kernels.hpp"]
 
 
 def hipcc() -> str:

@@ -202,8 +202,9 @@ __global__ void hyperbox_kernel(KParams P) {
         const int64_t k = work_item(P, q);
         const LpRef L = lp_ref(P, k);
         const double* c = P.c + L.col_off;
-        const double* lo = P.l + L.col_off;
-        const double* up = P.u + L.col_off;
+        const int64_t bo = P.box_shared ? 0 : L.col_off;  // one box for every LP, or its own
+        const double* lo = P.l + bo;
+        const double* up = P.u + bo;
         double* x = P.x + L.col_off;
         bool bad = false, empty = false;
         double acc = 0.0;
@@ -254,10 +255,13 @@ __global__ void __launch_bounds__(64) hyperbox_tile_kernel(KParams P) {
 #pragma unroll
             for (int q = 0; q < UNR; ++q) {
                 const int e = eb + q * 64 + lane;
-                const int64_t a = e0 + (e < ne ? e : 0);
+                const int ec = e < ne ? e : 0;
+                const int64_t a = e0 + ec;
+                // a shared box is read at the variable's index
+                const int64_t ab = P.box_shared ? (int64_t)(ec - (int)__umulhi((unsigned)ec, magic) * N) : a;
                 cv[q] = P.c[a];
-                lv[q] = P.l[a];
-                uv[q] = P.u[a];
+                lv[q] = P.l[ab];
+                uv[q] = P.u[ab];
             }
 #pragma unroll
             for (int q = 0; q < UNR; ++q) {
@@ -306,6 +310,58 @@ __global__ void __launch_bounds__(256) backward_hyperbox_flat_kernel(KParams P, 
         if (dc) dc[e] = ok ? gk * P.x[e] : 0.0;
         if (dl) dl[e] = ok && ci < 0.0 ? gk * ci : 0.0;
         if (du) du[e] = ok && !(ci < 0.0) ? gk * ci : 0.0;
+    }
+}
+
+// Adjoint of a shared box: dl_i = sum over hyperbox LPs k of g_k min(c_ki, 0)
+// and du_i of g_k max(c_ki, 0) (zero for LPs that are not OPTIMAL).  A fixed
+// summation order, independent of scheduling: block b sums LPs
+// [b * 1024, (b + 1) * 1024) -- each thread its four LPs t, t + 256, t + 512,
+// t + 768 in that order, then a pairwise tree over the 256 threads -- into
+// part[b]; box_shared_final then adds the block sums in block order.
+constexpr int kBoxRedLps = 1024;
+__global__ void __launch_bounds__(256) box_shared_partial_kernel(KParams P, const double* g, int n, double* part) {
+    __shared__ double s_l[256], s_u[256];
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * kBoxRedLps;
+    for (int i = 0; i < n; ++i) {
+        double al = 0.0, au = 0.0;
+        for (int r = 0; r < kBoxRedLps / 256; ++r) {
+            const int64_t k = k0 + t + r * 256;
+            if (k < P.count && lp_kind(P, k) == 1 && P.status[k] == ST_OPTIMAL) {
+                const double ci = P.c[lp_ref(P, k).col_off + i];
+                const double gk = g[k];
+                al = al + (ci < 0.0 ? gk * ci : 0.0);
+                au = au + (ci < 0.0 ? 0.0 : gk * ci);
+            }
+        }
+        s_l[t] = al;
+        s_u[t] = au;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) {
+                s_l[t] = s_l[t] + s_l[t + w];
+                s_u[t] = s_u[t] + s_u[t + w];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            part[(int64_t)blockIdx.x * 2 * n + i] = s_l[0];
+            part[(int64_t)blockIdx.x * 2 * n + n + i] = s_u[0];
+        }
+        __syncthreads();
+    }
+}
+__global__ void __launch_bounds__(256) box_shared_final_kernel(const double* part, int nblocks, int n, double* dl,
+                                                               double* du) {
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int b = 0; b < nblocks; ++b) acc = acc + part[(int64_t)b * 2 * n + i];
+        if (i < n) {
+            if (dl) dl[i] = acc;
+        } else if (du) {
+            du[i - n] = acc;
+        }
     }
 }
 
@@ -414,6 +470,14 @@ hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc
                                    hipStream_t s) {
     hipLaunchKernelGGL(backward_simplex_kernel, dim3(grid_for(P.count, 1, 1 << 16)), dim3(256), 0, s, P, g, dc,
                        db, dA);
+    return hipGetLastError();
+}
+int box_shared_blocks(int64_t count) { return (int)((count + kBoxRedLps - 1) / kBoxRedLps); }
+hipError_t launch_backward_box_shared(const KParams& P, int n, const double* g, double* part, double* dl, double* du,
+                                      hipStream_t s) {
+    const int nb = box_shared_blocks(P.count);
+    hipLaunchKernelGGL(box_shared_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, P, g, n, part);
+    hipLaunchKernelGGL(box_shared_final_kernel, dim3(1), dim3(256), 0, s, (const double*)part, nb, n, dl, du);
     return hipGetLastError();
 }
 hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,

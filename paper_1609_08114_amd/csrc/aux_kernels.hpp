@@ -45,6 +45,11 @@ hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc
                                    hipStream_t s);
 hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
                                     double* du, hipStream_t s);
+// Shared box: dl, du (length n) summed over the hyperbox LPs in a fixed
+// order; `part` holds 2 n doubles per block of box_shared_blocks(count).
+int box_shared_blocks(int64_t count);
+hipError_t launch_backward_box_shared(const KParams& P, int n, const double* g, double* part, double* dl, double* du,
+                                      hipStream_t s);
 
 // Shared-constraint kernel (simplex_reg.hip): tableau shape and launcher.
 hipError_t launch_shared(const KParams& P, int grid, hipStream_t s);

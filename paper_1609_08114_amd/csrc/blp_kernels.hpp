@@ -52,7 +52,9 @@ struct KParams {
     int32_t direct;       // 1: entry = direct_first + blockIdx.x, no queue
     int64_t chunk;        // shared-constraint mode: LPs taken per queue pop
     int32_t shared_in;    // 1: every LP reads A, b and sense at offset 0 (one shared constraint set)
+    int32_t box_shared;   // 1: every hyperbox LP reads l and u at offset 0 (one shared box)
     int64_t direct_first;
+    int64_t direct_end;   // kernels with several LPs per workgroup: positions >= direct_end are not taken (0: none)
     // streaming kernel workspace: one slot of ws_slot doubles per workgroup
     double* ws;
     int64_t ws_slot;

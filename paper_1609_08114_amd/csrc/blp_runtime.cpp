@@ -33,7 +33,8 @@ constexpr int kMaxCols = 4096;  // n + m + 1 (condensed columns, worst case)
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
-    hipError_t reserve(size_t want) {
+    // exact: allocate `want` bytes, not the 1.5x growth (memory-limited handles)
+    hipError_t reserve(size_t want, bool exact = false) {
         if (want <= bytes) return hipSuccess;
         if (p) {
             hipError_t e = hipFree(p);
@@ -41,7 +42,7 @@ struct DevBuf {
             p = nullptr;
             bytes = 0;
         }
-        size_t cap = std::max(want, bytes + bytes / 2);
+        size_t cap = exact ? want : std::max(want, bytes + bytes / 2);
         hipError_t e = hipMalloc(&p, cap);
         if (e != hipSuccess) {
             p = nullptr;
@@ -111,6 +112,10 @@ struct blp_handle_s {
     bool uniform = false;
     bool any_simplex = false, any_box = false;
     int64_t n_box = 0;
+    bool box_shared = false;
+    int32_t box_n = 0;      // n of the hyperbox LPs sharing one box
+    bool chunked = false;   // the last solve was split by mem_limit
+    DevBuf bwd_part;        // shared-box adjoint: per-block partial sums
 #ifdef BLP_PHASE_TIMERS
     unsigned long long* timers = nullptr;
 #endif
@@ -173,6 +178,14 @@ struct blp_handle_s {
 };
 
 static blp_error fail(blp_handle h, blp_error code, const char* fmt, ...);
+
+// Persistent grid of register variant v for `lps` LPs: its occupancy-sized
+// worker count, but no more workgroups than the LPs fill.
+static int reg_grid(blp_handle h, int v, int64_t lps) {
+    const int64_t per = h->variants[v].lps_per_block;
+    const int64_t need = (lps + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(h->reg_workers[v], need));
+}
 
 // Order this call's work after the previous call's (see order_ev).
 static hipError_t begin_call(blp_handle h, hipStream_t s) {
@@ -296,6 +309,14 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
         blp_destroy(h);
         return ce == hipErrorOutOfMemory ? BLP_ERR_NOMEM : BLP_ERR_HIP;
     }
+    if (o.tune_cache) {
+        const blp_error te = blp_load_tuning(h, o.tune_cache);
+        if (te != BLP_SUCCESS) {
+            blp_destroy(h);
+            return te;
+        }
+    }
+    h->opt.tune_cache = nullptr;  // the caller's string is not kept
     *out = h;
     return BLP_SUCCESS;
 }
@@ -355,6 +376,7 @@ void blp_destroy(blp_handle h) {
         h->pin_out[i].release();
     }
     h->shared_ctr.release();
+    h->bwd_part.release();
     delete h;
 }
 
@@ -374,6 +396,7 @@ struct SolvePlan {
     int32_t* binid = nullptr;
     int32_t* list = nullptr;   // unordered work lists (scatter output)
     int32_t* olist = nullptr;  // largest-first work lists (non-uniform batches)
+    int32_t box_n = 0;         // shared box: its length
 };
 
 // A device buffer for one solve: the handle's growable buffer `own`, or,
@@ -389,7 +412,7 @@ struct SolvePlan {
                             (arena)->cap, #own, want_);                                              \
             (ptr) = static_cast<decltype(ptr)>(p_);                                                  \
         } else {                                                                                     \
-            HIP_TRY(h, (own).reserve(want_));                                                        \
+            HIP_TRY(h, (own).reserve(want_, (h)->opt.mem_limit > 0));                                \
             (ptr) = static_cast<decltype(ptr)>((own).p);                                             \
         }                                                                                            \
     } while (0)
@@ -399,8 +422,9 @@ struct SolvePlan {
 // the streaming kernel (the autotuner times it on register-variant samples).
 // arena: the allocation-free entry point's scratch (every output must then
 // be given; nothing is allocated).
+// ws_budget (memory-limited handles): bytes the streaming workspace may take.
 static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp,
-                         bool stream_all = false, Arena* arena = nullptr) {
+                         bool stream_all = false, Arena* arena = nullptr, size_t ws_budget = 0) {
     const int64_t K = B->count;
     if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
     const bool uni = B->uniform != 0;
@@ -469,6 +493,17 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     }
     if (any_simplex && (!B->A || !B->b || !B->sense || !B->c)) return fail(h, BLP_ERR_ARG, "A, b, sense, c required");
     if (any_box && (!B->c || !B->l || !B->u)) return fail(h, BLP_ERR_ARG, "c, l, u required for hyperbox LPs");
+    // one shared box: every hyperbox LP has its length
+    sp.box_n = 0;
+    if (B->shared_box && any_box) {
+        for (int64_t k = 0; k < nmeta; ++k) {
+            if (h->h_kind[k] != BLP_KIND_HYPERBOX) continue;
+            if (sp.box_n == 0) sp.box_n = h->h_n[k];
+            if (h->h_n[k] != sp.box_n)
+                return fail(h, BLP_ERR_ARG, "LP %lld: a shared box needs every hyperbox LP to have n = %d",
+                            (long long)k, sp.box_n);
+        }
+    }
     if (!uni) {
         h->h_a_off.resize(K);
         h->h_row_off.resize(K);
@@ -564,6 +599,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.pivot_rule = h->opt.pivot_rule;
     P.layout = h->opt.layout;
     P.seed = h->opt.seed;
+    P.box_shared = (B->shared_box && any_box) ? 1 : 0;
 #ifdef BLP_PHASE_TIMERS
     P.timers = h->timers;
 #endif
@@ -641,6 +677,9 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
                             arena->cap, sizeof(double) * slot);
             sp.gm_workers = (int)std::min<int64_t>(sp.gm_workers, fit);
         }
+        if (ws_budget > 0)
+            sp.gm_workers = (int)std::max<int64_t>(
+                1, std::min<int64_t>(sp.gm_workers, (int64_t)(ws_budget / (sizeof(double) * slot))));
         BUF_TRY(h, arena, h->ws, sizeof(double) * slot * (size_t)sp.gm_workers, P.ws);
         P.ws_slot = (int64_t)slot;
         P.ws_ld = sp.gm_ld;
@@ -723,7 +762,7 @@ static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s, 
         what = "event record";
         if (err == hipSuccess) {
             what = "kernel launch";
-            err = v < nreg ? h->variants[v].launch(Q, (int)std::min<int64_t>(h->reg_workers[v], K), st)
+            err = v < nreg ? h->variants[v].launch(Q, reg_grid(h, v, K), st)
                            : launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, K), sp.gm_lds, st, sp.gm_deep);
         }
         if (err == hipSuccess) {
@@ -772,10 +811,12 @@ static blp_error enqueue_baseline(blp_handle h, SolvePlan& sp, hipStream_t s) {
         KParams Q = P;
         Q.bin = v;
         const int64_t chunk = v == nreg ? sp.gm_workers : (mode == BLP_MODE_GRID ? nv : 1);
+        const int64_t per = v < nreg ? h->variants[v].lps_per_block : 1;  // LPs per workgroup
         HIP_TRY(h, h->mark(v, true, s));
         for (int64_t first = 0; first < nv; first += chunk) {
             Q.direct_first = first;
-            const int grid = (int)std::min<int64_t>(chunk, nv - first);
+            Q.direct_end = std::min<int64_t>(first + chunk, nv);
+            const int grid = (int)((std::min<int64_t>(chunk, nv - first) + per - 1) / per);
             if (v == nreg) {
                 if (mode == BLP_MODE_GRID) {
                     HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s, sp.gm_deep));
@@ -825,6 +866,165 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
     return g;
 }
 
+static void record_solve(blp_handle h, const SolvePlan& sp, int64_t K) {
+    h->last = sp.P;
+    h->last.direct = 0;
+    h->count = K;
+    h->uniform = sp.uni;
+    h->any_simplex = sp.any_simplex;
+    h->any_box = sp.any_box;
+    h->n_box = sp.n_box;
+    h->box_shared = sp.P.box_shared != 0;
+    h->box_n = sp.box_n;
+    h->chunked = false;
+    h->solved = true;
+}
+
+static blp_error enqueue_eager(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    blp_error e = enqueue_binning(h, sp, s);
+    if (e != BLP_SUCCESS) return e;
+    e = h->opt.mode == BLP_MODE_PERSISTENT ? enqueue_persistent(h, sp, s) : enqueue_baseline(h, sp, s);
+    if (e != BLP_SUCCESS) return e;
+    return enqueue_hyperbox(h, sp, s);
+}
+
+// A handle with mem_limit S: everything the call allocates fits in S bytes.
+// The result buffers the handle provides (outputs passed as NULL), the bin
+// counters and one streaming workspace slot of the batch's largest LP are
+// fixed; each LP adds Y bytes of metadata and work lists (8 for a uniform
+// batch, 48 otherwise).  The batch is solved in consecutive chunks of
+// N = (S - fixed) / Y LPs -- the batch capacity of Sec. 4.5, Eq. (5) -- on
+// the caller's stream, one after another, into the caller's (or the
+// handle's) result buffers; the streaming kernel gets as many workspace slots
+// as the rest of the limit holds.  The handle's buffers are released first
+// and then sized exactly, so the call never holds more than S.
+static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s) {
+    const int64_t K = B->count;
+    if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
+    const bool uni = B->uniform != 0;
+    const int64_t nmeta = uni ? 1 : K;
+    const uint64_t limit = h->opt.mem_limit;
+    std::vector<int64_t> ao, ro, co;  // packed offsets for NULL offset arrays
+    int64_t tot_m = 0, tot_n = 0, max_slot = 0;
+    bool any_simplex = false;
+    {
+        int64_t a = 0, r = 0, c = 0;
+        if (!uni) {
+            ao.resize(K);
+            ro.resize(K);
+            co.resize(K);
+        }
+        for (int64_t k = 0; k < nmeta; ++k) {
+            const int m = B->m[k], n = B->n[k];
+            if (m < 0 || n < 0 || m > kMaxM || n > kMaxCols)
+                return fail(h, BLP_ERR_ARG, "LP %lld: size out of range", (long long)k);
+            if (B->kind[k] == BLP_KIND_SIMPLEX) {
+                any_simplex = true;
+                max_slot = std::max<int64_t>(max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
+            }
+            if (!uni) {
+                ao[k] = B->a_off ? B->a_off[k] : a;
+                ro[k] = B->row_off ? B->row_off[k] : r;
+                co[k] = B->col_off ? B->col_off[k] : c;
+                tot_m = std::max(tot_m, ro[k] + m);
+                tot_n = std::max(tot_n, co[k] + n);
+                a += (int64_t)m * n;
+                r += m;
+                c += n;
+            }
+        }
+        if (uni) {
+            tot_m = K * (int64_t)B->m[0];
+            tot_n = K * (int64_t)B->n[0];
+        }
+    }
+    const bool own_st = !out || !out->status, own_it = !out || !out->iters, own_ob = !out || !out->obj;
+    const bool own_x = !out || !out->x, own_y = !out || !out->y;
+    const size_t out_bytes = (own_st ? 4 * (size_t)K : 0) + (own_it ? 4 * (size_t)K : 0) +
+                             (own_ob ? 8 * (size_t)K : 0) + (own_x ? 8 * (size_t)std::max<int64_t>(1, tot_n) : 0) +
+                             (own_y ? 8 * (size_t)std::max<int64_t>(1, tot_m) : 0);
+    const size_t counters = sizeof(int32_t) * (4 + (size_t)kBinStripes) * (h->nreg + 2);
+    const size_t slot = any_simplex ? sizeof(double) * (size_t)max_slot : 0;
+    const size_t per_lp = uni ? 8 : 48;
+    const size_t fixed = out_bytes + counters + slot;
+    if (fixed + per_lp > limit)
+        return fail(h, BLP_ERR_NOMEM,
+                    "mem_limit of %llu bytes: %zu bytes of results, %zu of bin counters and a %zu-byte workspace "
+                    "slot leave no room for one LP (%zu bytes)",
+                    (unsigned long long)limit, out_bytes, counters, slot, per_lp);
+    const int64_t cap = (int64_t)std::min<uint64_t>((limit - fixed) / per_lp, (uint64_t)K);
+    // the buffers are sized for this call alone
+    for (DevBuf* b : {&h->meta, &h->counters, &h->binid, &h->list, &h->olist, &h->ws, &h->own_status, &h->own_iters,
+                      &h->own_obj, &h->own_x, &h->own_y})
+        b->release();
+    blp_outputs o = out ? *out : blp_outputs{};
+    if (own_st) HIP_TRY(h, h->own_status.reserve(4 * (size_t)K, true));
+    if (own_it) HIP_TRY(h, h->own_iters.reserve(4 * (size_t)K, true));
+    if (own_ob) HIP_TRY(h, h->own_obj.reserve(8 * (size_t)K, true));
+    if (own_x) HIP_TRY(h, h->own_x.reserve(8 * (size_t)std::max<int64_t>(1, tot_n), true));
+    if (own_y) HIP_TRY(h, h->own_y.reserve(8 * (size_t)std::max<int64_t>(1, tot_m), true));
+    if (own_st) o.status = h->own_status.as<int32_t>();
+    if (own_it) o.iters = h->own_iters.as<int32_t>();
+    if (own_ob) o.obj = h->own_obj.as<double>();
+    if (own_x) o.x = h->own_x.as<double>();
+    if (own_y) o.y = h->own_y.as<double>();
+    SolvePlan sp;
+    int nchunks = 0;
+    for (int64_t k0 = 0; k0 < K; k0 += cap, ++nchunks) {
+        const int64_t kc = std::min<int64_t>(cap, K - k0);
+        blp_batch sub = *B;
+        sub.count = kc;
+        blp_outputs os = o;
+        os.status = o.status + k0;
+        os.iters = o.iters + k0;
+        os.obj = o.obj + k0;
+        if (uni) {
+            const int64_t m = B->m[0], n = B->n[0];
+            if (B->A) sub.A = B->A + k0 * m * n;
+            if (B->b) sub.b = B->b + k0 * m;
+            if (B->sense) sub.sense = B->sense + k0 * m;
+            if (B->c) sub.c = B->c + k0 * n;
+            if (!B->shared_box) {
+                if (B->l) sub.l = B->l + k0 * n;
+                if (B->u) sub.u = B->u + k0 * n;
+            }
+            os.x = o.x + k0 * n;
+            os.y = o.y + k0 * m;
+        } else {  // offsets stay absolute
+            sub.m = B->m + k0;
+            sub.n = B->n + k0;
+            sub.kind = B->kind + k0;
+            sub.a_off = ao.data() + k0;
+            sub.row_off = ro.data() + k0;
+            sub.col_off = co.data() + k0;
+        }
+        const size_t ws_budget = (size_t)(limit - out_bytes - counters - per_lp * (size_t)kc);
+        blp_error e = prepare(h, &sub, &os, s, sp, false, nullptr, std::max<size_t>(ws_budget, 1));
+        if (e != BLP_SUCCESS) return e;
+        e = enqueue_eager(h, sp, s);
+        if (e != BLP_SUCCESS) return e;
+    }
+    HIP_TRY(h, hipGetLastError());
+    // the handle describes the whole batch (results, host metadata); the
+    // work lists are those of the last chunk
+    record_solve(h, sp, K);
+    h->last.status = o.status;
+    h->last.iters = o.iters;
+    h->last.obj = o.obj;
+    h->last.x = o.x;
+    h->last.y = o.y;
+    h->h_m.assign(B->m, B->m + nmeta);
+    h->h_n.assign(B->n, B->n + nmeta);
+    h->h_kind.assign(B->kind, B->kind + nmeta);
+    if (!uni) {
+        h->h_a_off = ao;
+        h->h_row_off = ro;
+        h->h_col_off = co;
+    }
+    h->chunked = nchunks > 1;
+    return BLP_SUCCESS;
+}
+
 blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* out, void* stream) {
     if (!h) return BLP_ERR_ARG;
     h->err.clear();
@@ -840,6 +1040,12 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
         return BLP_SUCCESS;
     }
     HIP_TRY(h, begin_call(h, s));
+    if (h->opt.mem_limit > 0) {
+        const blp_error le = solve_limited(h, B, out, s);
+        if (le != BLP_SUCCESS) return le;
+        HIP_TRY(h, end_call(h, s));
+        return BLP_SUCCESS;
+    }
     SolvePlan sp;
     blp_error e = prepare(h, B, out, s, sp);
     if (e != BLP_SUCCESS) return e;
@@ -875,24 +1081,12 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
         }
         HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     } else {
-        e = enqueue_binning(h, sp, s);
-        if (e != BLP_SUCCESS) return e;
-        e = h->opt.mode == BLP_MODE_PERSISTENT ? enqueue_persistent(h, sp, s) : enqueue_baseline(h, sp, s);
-        if (e != BLP_SUCCESS) return e;
-        e = enqueue_hyperbox(h, sp, s);
+        e = enqueue_eager(h, sp, s);
         if (e != BLP_SUCCESS) return e;
     }
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, end_call(h, s));
-
-    h->last = sp.P;
-    h->last.direct = 0;
-    h->count = K;
-    h->uniform = sp.uni;
-    h->any_simplex = sp.any_simplex;
-    h->any_box = sp.any_box;
-    h->n_box = sp.n_box;
-    h->solved = true;
+    record_solve(h, sp, K);
     return BLP_SUCCESS;
 }
 
@@ -987,7 +1181,7 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         if (v < 0) return fail(h, BLP_ERR_STATE, "no register variant of the shared tile shape");
         P.shared_in = 1;
         HIP_TRY(h, launch_reset(P.bin_head, 1, s));
-        HIP_TRY(h, h->variants[v].launch(P, (int)std::min<int64_t>(h->reg_workers[v], count), s));
+        HIP_TRY(h, h->variants[v].launch(P, reg_grid(h, v, count), s));
         HIP_TRY(h, end_call(h, s));
         return BLP_SUCCESS;
     }
@@ -1034,6 +1228,9 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         r += m[k];
         c += n[k];
     }
+    int64_t box_n = 0;  // shared box: its length (that of any hyperbox LP)
+    for (int64_t k = 0; k < K && B->shared_box && !box_n; ++k)
+        if (kind[k] == BLP_KIND_HYPERBOX) box_n = n[k];
     if (chunks <= 0) chunks = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, K / 1024));
     chunks = (int32_t)std::min<int64_t>(chunks, K);
     for (int i = 0; i < 2; ++i) {
@@ -1090,8 +1287,13 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         HIP_TRY(h, up(db, B->b ? B->b + rr.lo : nullptr, sizeof(double) * nr));
         HIP_TRY(h, up(dsense, B->sense ? B->sense + rr.lo : nullptr, (size_t)nr));
         HIP_TRY(h, up(dc, B->c ? B->c + rc.lo : nullptr, sizeof(double) * nc));
-        HIP_TRY(h, up(dl, B->l ? B->l + rc.lo : nullptr, sizeof(double) * nc));
-        HIP_TRY(h, up(du, B->u ? B->u + rc.lo : nullptr, sizeof(double) * nc));
+        if (B->shared_box) {  // the one box (at most nc long: some LP of the piece has its length)
+            HIP_TRY(h, up(dl, B->l ? B->l : nullptr, sizeof(double) * std::min<int64_t>(box_n, nc)));
+            HIP_TRY(h, up(du, B->u ? B->u : nullptr, sizeof(double) * std::min<int64_t>(box_n, nc)));
+        } else {
+            HIP_TRY(h, up(dl, B->l ? B->l + rc.lo : nullptr, sizeof(double) * nc));
+            HIP_TRY(h, up(du, B->u ? B->u + rc.lo : nullptr, sizeof(double) * nc));
+        }
         std::vector<int64_t> cao(Kc), cro(Kc), cco(Kc);
         for (int64_t k = k0; k < k1; ++k) {
             cao[k - k0] = ao[k] - ra.lo;
@@ -1101,6 +1303,7 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         blp_batch cb{};
         cb.count = Kc;
         cb.uniform = uni ? 1 : 0;
+        cb.shared_box = B->shared_box;
         cb.m = uni ? m.data() : m.data() + k0;
         cb.n = uni ? n.data() : n.data() + k0;
         cb.kind = uni ? kind.data() : kind.data() + k0;
@@ -1192,11 +1395,11 @@ blp_error blp_get_solution(blp_handle h, int64_t k, int32_t* status, double* obj
 }
 
 blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, double* obj, double* x,
-                                 double* y) {
+                                 double* y, int32_t on_device) {
     if (!h) return BLP_ERR_ARG;
     if (!h->solved) return fail(h, BLP_ERR_STATE, "no solve yet");
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, wait_last(h));
+    if (!on_device) HIP_TRY(h, wait_last(h));
     const int64_t K = h->count;
     if (K == 0) return BLP_SUCCESS;
     int64_t tot_m = 0, tot_n = 0;
@@ -1212,6 +1415,17 @@ blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, 
         tot_n = K * (int64_t)h->h_n[0];
     }
     const KParams& P = h->last;
+    if (on_device) {
+        // device to device on the last solve's stream (ordered after it)
+        const hipStream_t s = h->last_stream;
+        if (status)
+            HIP_TRY(h, hipMemcpyAsync(status, P.status, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
+        if (iters) HIP_TRY(h, hipMemcpyAsync(iters, P.iters, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
+        if (obj) HIP_TRY(h, hipMemcpyAsync(obj, P.obj, sizeof(double) * K, hipMemcpyDeviceToDevice, s));
+        if (x && tot_n > 0) HIP_TRY(h, hipMemcpyAsync(x, P.x, sizeof(double) * tot_n, hipMemcpyDeviceToDevice, s));
+        if (y && tot_m > 0) HIP_TRY(h, hipMemcpyAsync(y, P.y, sizeof(double) * tot_m, hipMemcpyDeviceToDevice, s));
+        return BLP_SUCCESS;
+    }
     if (status) HIP_TRY(h, hipMemcpy(status, P.status, sizeof(int32_t) * K, hipMemcpyDeviceToHost));
     if (iters) HIP_TRY(h, hipMemcpy(iters, P.iters, sizeof(int32_t) * K, hipMemcpyDeviceToHost));
     if (obj) HIP_TRY(h, hipMemcpy(obj, P.obj, sizeof(double) * K, hipMemcpyDeviceToHost));
@@ -1225,6 +1439,7 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
     if (!h) return BLP_ERR_ARG;
     h->err.clear();
     if (!h->solved) return fail(h, BLP_ERR_STATE, "backward before any solve");
+    if (h->chunked) return fail(h, BLP_ERR_STATE, "backward after a solve that mem_limit split into chunks");
     if (h->count == 0) return BLP_SUCCESS;
     if (!g) return fail(h, BLP_ERR_ARG, "g is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1235,7 +1450,17 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
     if (h->any_box && (dc || dl || du)) {
         KParams Q = P;
         Q.bin = h->nreg + 1;
-        HIP_TRY(h, launch_backward_hyperbox(Q, P.list ? h->n_box : h->count, g, dc, dl, du, s));
+        if (h->box_shared) {
+            // per-LP dc; dl, du summed over the LPs into the one box
+            if (dc) HIP_TRY(h, launch_backward_hyperbox(Q, P.list ? h->n_box : h->count, g, dc, nullptr, nullptr, s));
+            if (dl || du) {
+                const size_t nb = (size_t)box_shared_blocks(P.count);
+                HIP_TRY(h, h->bwd_part.reserve(sizeof(double) * 2 * (size_t)h->box_n * nb));
+                HIP_TRY(h, launch_backward_box_shared(Q, h->box_n, g, h->bwd_part.as<double>(), dl, du, s));
+            }
+        } else {
+            HIP_TRY(h, launch_backward_hyperbox(Q, P.list ? h->n_box : h->count, g, dc, dl, du, s));
+        }
     }
     HIP_TRY(h, end_call(h, s));
     return BLP_SUCCESS;
@@ -1370,7 +1595,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
                 HIP_TRY(h, launch_reset(tb + 2, 1, s));
                 HIP_TRY(h, hipEventRecord(e0, s));
                 if (w < nreg) {
-                    HIP_TRY(h, h->variants[w].launch(Q, (int)std::min<int64_t>(h->reg_workers[w], S), s));
+                    HIP_TRY(h, h->variants[w].launch(Q, reg_grid(h, w, S), s));
                 } else {
                     HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, S), sp.gm_lds, s, sp.gm_deep));
                 }

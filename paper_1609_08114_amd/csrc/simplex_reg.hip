@@ -26,6 +26,7 @@
 #include "blp_kernels.hpp"
 #include "simplex_blk.hpp"
 #include "simplex_common.hpp"
+#include "simplex_lane.hpp"
 #include "variants.hpp"
 
 namespace blp {
@@ -401,6 +402,16 @@ static const void* kernel_ptr_blk() {
     return reinterpret_cast<const void*>(&simplex_blk_kernel<NW, GC, RB, CB, WPE>);
 }
 
+template <int R, int C, int NWV, int WPE>
+static hipError_t launch_lane(const KParams& P, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((simplex_lane_kernel<R, C, NWV, WPE>), dim3(grid), dim3(NWV * 64), 0, s, P);
+    return hipGetLastError();
+}
+template <int R, int C, int NWV, int WPE>
+static const void* kernel_ptr_lane() {
+    return reinterpret_cast<const void*>(&simplex_lane_kernel<R, C, NWV, WPE>);
+}
+
 // Shared-constraint mode (one A, b; many objectives): the block kernel with a
 // 112 x 112 tile.
 constexpr int kSharedRows = 112, kSharedCols = 112;
@@ -417,9 +428,12 @@ void shared_shape(int* rows, int* cols) {
 
 #define BLP_BLK_VARIANT(NAME, NW, GC, RB, CB, WPE)                                                    \
     {NAME, (NW) * 64, (NW) * 64 / (GC) * (RB), (GC) * (CB), &launch_blk<NW, GC, RB, CB, WPE>, \
-     &kernel_ptr_blk<NW, GC, RB, CB, WPE>},
-#define BLP_REG_VARIANT(NAME, NW, TC, CT, WPE) \
-    {NAME, (NW) * 64, (NW) * 64 / (TC), (TC) * (CT), &launch_reg<NW, TC, CT, WPE>, &kernel_ptr<NW, TC, CT, WPE>},
+     &kernel_ptr_blk<NW, GC, RB, CB, WPE>, 1},
+#define BLP_REG_VARIANT(NAME, NW, TC, CT, WPE)                                                                  \
+    {NAME, (NW) * 64, (NW) * 64 / (TC), (TC) * (CT), &launch_reg<NW, TC, CT, WPE>, &kernel_ptr<NW, TC, CT, WPE>, \
+     1},
+#define BLP_LANE_VARIANT(NAME, R, C, NWV, WPE) \
+    {NAME, (NWV) * 64, R, C, &launch_lane<R, C, NWV, WPE>, &kernel_ptr_lane<R, C, NWV, WPE>, (NWV) * 64},
 
 const RegVariant* reg_variants(int* count) {
     static const RegVariant table[] = {BLP_REG_VARIANT_LIST};

@@ -1,12 +1,17 @@
 // Table of register-tile kernel variants.  Each entry fixes the thread grid
-// of simplex_reg_kernel:
-//   (name, waves, TC threads per tableau row, CT columns per thread, target
-//    waves per SIMD)
-// giving a maximum tableau of 64*waves/TC rows by TC*CT columns (objective
-// rows and the rhs column included).  The scheduler sends each LP
-// to the fitting variant of smallest area, the first in this order among
-// equal areas: the row-tile w4/w8 variants (the first design, kept for
-// comparison and the autotuner) come after the block tiles of their shapes.
+// of one kernel template:
+//   BLP_LANE_VARIANT (name, R rows, C columns, waves per workgroup, waves
+//     per SIMD): simplex_lane_kernel, one LP per lane (64 LPs per wave);
+//   BLP_REG_VARIANT (name, waves, TC threads per tableau row, CT columns per
+//     thread, waves per SIMD): simplex_reg_kernel, one LP per workgroup,
+//     a tableau of 64*waves/TC rows by TC*CT columns;
+//   BLP_BLK_VARIANT (name, waves, GC column groups, RB rows and CB columns
+//     per thread, waves per SIMD): simplex_blk_kernel, one LP per workgroup.
+// Shapes count the objective rows and the rhs column.  The scheduler sends
+// each LP to the fitting variant of smallest area, the first in this order
+// among equal areas: the lane variants come first, and the row-tile w4/w8
+// variants (the first design, kept for comparison and the autotuner) come
+// after the block tiles of their shapes.
 #pragma once
 
 #include "blp_kernels.hpp"
@@ -20,6 +25,7 @@ struct RegVariant {
     int max_cols;
     hipError_t (*launch)(const KParams&, int grid, hipStream_t);
     const void* (*kernel)();
+    int lps_per_block;  // LPs a workgroup takes at once (lane kernel: one per thread)
 };
 
 // Host-side table of the compiled variants.
@@ -27,6 +33,8 @@ const RegVariant* reg_variants(int* count);
 
 // clang-format off
 #define BLP_REG_VARIANT_LIST                                  \
+    BLP_LANE_VARIANT("l64_r8_c8",    8, 8,  4, 2)            \
+    BLP_LANE_VARIANT("l64_r7_c11",   7, 11, 4, 2)            \
     BLP_REG_VARIANT("w1_r8_c8",      1, 8,   1, 4)           \
     BLP_REG_VARIANT("w1_r16_c16",    1, 4,   4, 4)           \
     BLP_REG_VARIANT("w1_r32_c32",    1, 2,  16, 2)           \

@@ -110,7 +110,10 @@ def compare_scattered(hb: lpgen.Batch, g: dict, o: dict, tag: str = "") -> None:
         yw[hb.row_off[k]:hb.row_off[k] + hb.m[k]] = True
     gg = dict(g)
     oo = dict(o)
+    def fit(a, size):  # outputs may end at the last LP's range, before the inputs' padding
+        a = np.asarray(a)[:size]
+        return np.concatenate([a, np.zeros(size - a.size, a.dtype)]) if a.size < size else a
     for d in (gg, oo):
-        d["x"] = np.where(xw, np.asarray(d["x"])[:xw.size], 0.0)
-        d["y"] = np.where(yw, np.asarray(d["y"])[:yw.size], 0.0)
+        d["x"] = np.where(xw, fit(d["x"], xw.size), 0.0)
+        d["y"] = np.where(yw, fit(d["y"], yw.size), 0.0)
     compare(hb, gg, oo, strict=True, tag=tag)

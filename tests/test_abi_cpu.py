@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_host_only_calls():
-    assert blp.blp_abi_version() == 1
+    assert blp.blp_abi_version() == 2
     o = blp.blp_options_default()
     assert o.device == 0 and o.mode == 0 and o.variant == -1 and o.max_iter == 0
     vs = blp.variants()
@@ -65,3 +65,26 @@ def test_create_without_gpu_reports_error():
     h = ctypes.c_void_p()
     rc = blp.lib().blp_create(ctypes.byref(h), None)
     assert rc in (blp.BLP_ERR_HIP, blp.BLP_ERR_ARG) and not h.value
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures of the binding have the C header's field
+    offsets and sizes (compiled and printed by gcc)."""
+    src = tmp_path / "layout.c"
+    fields = {"blp_options": [f for f, _ in blp.blp_options._fields_],
+              "blp_batch": [f for f, _ in blp.blp_batch._fields_],
+              "blp_outputs": [f for f, _ in blp.blp_outputs._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "blp.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for st, cls in (("blp_options", blp.blp_options), ("blp_batch", blp.blp_batch), ("blp_outputs", blp.blp_outputs)):
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)

@@ -12,9 +12,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _check_sample(cfg, K, part=None, S=400, seed=0):
+    print(f"[fullsize] cfg {cfg} {part or ''} K={K}: generating", flush=True)
     hb = lpgen.config(cfg, range(K), part=part) if part else lpgen.config(cfg, range(K))
-    print(f"[fullsize] cfg {cfg} {part or ''} K={K}", flush=True)
+    print(f"[fullsize] cfg {cfg} {part or ''} K={K}: solving", flush=True)
     g = gpu_solve(hb)
+    print(f"[fullsize] cfg {cfg} {part or ''}: oracle on {min(S, K)} sampled LPs", flush=True)
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(K, size=min(S, K), replace=False))
     sub = lpgen.config(cfg, idx, part=part) if part else lpgen.config(cfg, idx)
@@ -30,6 +32,7 @@ def _check_sample(cfg, K, part=None, S=400, seed=0):
     gs["x"] = np.concatenate(xs)
     gs["y"] = np.concatenate(ys) if ys else np.zeros(0)
     compare(sub, gs, o, strict=True, tag=f"cfg{cfg}{part or ''}-full")
+    del hb
     return g
 
 
@@ -42,6 +45,23 @@ def test_workload2_full_batch():
 def test_workload3_full_batch():
     # 10,000 type-2 LPs, m = n = 200 (streaming kernel), ~2,000 pivots each
     _check_sample(3, 10_000, S=24, seed=3)
+
+
+def test_workload4_full_batch():
+    # the uneven batch at its stated size: 200,000 LPs with m, n ~ U{5..300}
+    # (40% type 1, 40% type 2, 20% hyperbox) in one persistent solve (every
+    # size class: register tiles, streaming kernel, hyperbox); 2,000 seeded
+    # random LPs recomputed by the oracle, strict
+    g = _check_sample(4, 200_000, S=2000, seed=4)
+    assert (g["status"] == 0).all()
+    bins = g["bins"]
+    assert bins.sum() == 200_000 and bins[-1] > 30_000 and bins[-2] > 0
+
+
+def test_workload5_simplex_full():
+    # 20,000 type-1 LPs with m = n ~ U{20..150} (several register variants)
+    g = _check_sample(5, 20_000, part="simplex", S=2000, seed=5)
+    assert (g["status"] == 0).all()
 
 
 def test_workload5_hyperbox_full():

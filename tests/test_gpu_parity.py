@@ -200,3 +200,55 @@ def test_determinism():
     b = gpu_solve(hb)
     for k in ("obj", "x", "y"):
         assert np.array_equal(a[k].view(np.int64), b[k].view(np.int64))
+
+
+def test_lane_kernel_tiny_lps():
+    """The smallest size class runs one LP per lane (64 per wave): a few
+    thousand tiny LPs of every outcome, strict against the oracle, spread
+    over both lane variants and several waves with a partial last wave; the
+    grid and one-LP-per-launch modes and the random entering rule give the
+    same bits as the other register kernels."""
+    import paper_1609_08114_amd as blp
+    rng = np.random.default_rng(23)
+    lps = []
+    for t in range(3001):
+        m = int(rng.integers(1, 6))
+        n = int(rng.integers(1, 6))
+        if t % 3 == 0:  # continuous, through an interior point, mixed senses
+            A = rng.uniform(-2, 10, size=(m, n))
+            x0 = rng.uniform(0.5, 2.0, size=n)
+            sense = rng.integers(0, 2, size=m).astype(np.int8)
+            ax = A @ x0
+            b = np.where(sense == 0, ax + rng.uniform(0.5, 3, m), ax - rng.uniform(0.5, 3, m))
+            c = rng.uniform(-1, 5, size=n)
+        else:
+            A = rng.integers(-3, 7, size=(m, n)).astype(float)
+            b = rng.integers(-4, 11, size=m).astype(float)
+            c = rng.integers(-2, 6, size=n).astype(float)
+            sense = rng.integers(0, 2, size=m).astype(np.int8)
+        lps.append(dict(A=A, b=b, c=c, sense=sense))
+    hb = crafted_batch(lps)
+    g, o = _both(hb, tag="lane-tiny")
+    names = [v[0] for v in blp.variants()]
+    lane = [i for i, nm in enumerate(names) if nm.startswith("l64_")]
+    assert len(lane) == 2 and all(g["bins"][i] > 64 for i in lane), g["bins"]
+    assert set(np.unique(o["status"])) >= {0, 1, 2}
+    sub = crafted_batch(lps[:700])
+    a = gpu_solve(sub)
+    for mode in (1, 2):
+        b = gpu_solve(sub, mode=mode)
+        for k in ("status", "iters"):
+            assert np.array_equal(a[k], b[k]), (mode, k)
+        for k in ("obj", "x", "y"):
+            assert np.array_equal(a[k].view(np.int64), b[k].view(np.int64)), (mode, k)
+    # random entering rule: the lane kernel and the row-tile kernel draw the
+    # same pivots
+    w1 = names.index("w1_r8_c8")
+    cfg1 = lpgen.config(1, range(1000))
+    r_lane = gpu_solve(cfg1, variant=lane[0], pivot_rule=blp.BLP_RULE_RPC, seed=3)
+    r_row = gpu_solve(cfg1, variant=w1, pivot_rule=blp.BLP_RULE_RPC, seed=3)
+    assert r_lane["bins"][lane[0]] == 1000
+    for k in ("status", "iters"):
+        assert np.array_equal(r_lane[k], r_row[k]), k
+    for k in ("obj", "x", "y"):
+        assert np.array_equal(r_lane[k].view(np.int64), r_row[k].view(np.int64)), k
