@@ -21,14 +21,12 @@
 #include "aux_kernels.hpp"
 #include "blp.h"
 #include "blp_kernels.hpp"
+#include "host_plan.hpp"
 #include "variants.hpp"
 
 using namespace blp;
 
 namespace {
-
-constexpr int kMaxM = 2046;     // rows of one LP
-constexpr int kMaxCols = 4096;  // n + m + 1 (condensed columns, worst case)
 
 struct DevBuf {
     void* p = nullptr;
@@ -106,8 +104,7 @@ struct blp_handle_s {
     // captured); a call on another stream first waits for it.
     hipEvent_t order_ev = nullptr;
     bool order_pending = false;
-    std::vector<int32_t> h_m, h_n, h_kind;
-    std::vector<int64_t> h_row_off, h_col_off, h_a_off;
+    Plan plan;  // host metadata of the last solve (plan_batch)
     int64_t count = 0;
     bool uniform = false;
     bool any_simplex = false, any_box = false;
@@ -426,106 +423,42 @@ struct SolvePlan {
 static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s, SolvePlan& sp,
                          bool stream_all = false, Arena* arena = nullptr, size_t ws_budget = 0) {
     const int64_t K = B->count;
-    if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
     const bool uni = B->uniform != 0;
-    const int64_t nmeta = uni ? 1 : K;
-    h->h_m.assign(B->m, B->m + nmeta);
-    h->h_n.assign(B->n, B->n + nmeta);
-    h->h_kind.assign(B->kind, B->kind + nmeta);
-    bool any_simplex = false, any_box = false;
-    int64_t n_box = 0, tot_a = 0, tot_m = 0, tot_n = 0;
-    int max_m = 0, max_cols = 0;
-    int64_t max_slot = 0;       // largest streaming tableau (ldk x (n + m + 1) doubles)
-    int64_t n_may_stream = 0;   // simplex LPs no register variant is sure to hold
-    const bool remap_streams = [&] {
-        for (int v = 0; v < h->nreg; ++v)
-            if (h->remap[v] >= h->nreg) return true;
-        return false;
-    }();
-    sp.gm_deep = false;
-    // no register tile holds the LP even without artificial columns
-    auto sure_stream = [&](int m, int n) {
-        if (h->opt.variant == -2) return true;
-        for (int v = 0; v < h->nreg; ++v) {
-            if (h->opt.variant >= 0 && v != h->opt.variant) continue;
-            if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + 1) return false;
-        }
-        return true;
-    };
-    auto sure_register = [&](int m, int n) {
-        if (stream_all || h->opt.variant == -2 || remap_streams) return false;
-        for (int v = 0; v < h->nreg; ++v) {
-            if (h->opt.variant >= 0 && v != h->opt.variant) continue;
-            if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + m + 1) return true;
-        }
-        return false;
-    };
-    for (int64_t k = 0; k < nmeta; ++k) {
-        const int m = h->h_m[k], n = h->h_n[k], kd = h->h_kind[k];
-        if (kd == BLP_KIND_SIMPLEX) {
-            if (m < 1 || n < 1) return fail(h, BLP_ERR_ARG, "LP %lld: simplex LP needs m >= 1 and n >= 1", (long long)k);
-            if (m > kMaxM || (int64_t)n + m + 1 > kMaxCols)
-                return fail(h, BLP_ERR_TOO_LARGE, "LP %lld: m=%d n=%d exceeds m <= %d, n + m + 1 <= %d",
-                            (long long)k, m, n, kMaxM, kMaxCols);
-            any_simplex = true;
-            max_m = std::max(max_m, m);
-            max_cols = std::max(max_cols, n + m + 1);
-            max_slot = std::max<int64_t>(max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
-            if (!sure_register(m, n)) ++n_may_stream;
-            if (sure_stream(m, n)) sp.gm_deep = true;
-        } else if (kd == BLP_KIND_HYPERBOX) {
-            if (m != 0 || n < 1) return fail(h, BLP_ERR_ARG, "LP %lld: hyperbox LP needs m == 0 and n >= 1", (long long)k);
-            any_box = true;
-            ++n_box;
-        } else {
-            return fail(h, BLP_ERR_ARG, "LP %lld: kind %d is not 0 or 1", (long long)k, kd);
-        }
-        tot_a += (int64_t)m * n;
-        tot_m += m;
-        tot_n += n;
+    std::vector<VariantShape> shapes((size_t)h->nreg);
+    bool remap_streams = false;
+    for (int v = 0; v < h->nreg; ++v) {
+        shapes[v] = {h->variants[v].max_rows, h->variants[v].max_cols};
+        remap_streams |= h->remap[v] >= h->nreg;
     }
-    if (uni) {
-        n_may_stream *= K;
-        n_box *= K;
-        tot_a *= K;
-        tot_m *= K;
-        tot_n *= K;
-    }
-    if (any_simplex && (!B->A || !B->b || !B->sense || !B->c)) return fail(h, BLP_ERR_ARG, "A, b, sense, c required");
-    if (any_box && (!B->c || !B->l || !B->u)) return fail(h, BLP_ERR_ARG, "c, l, u required for hyperbox LPs");
-    // one shared box: every hyperbox LP has its length
-    sp.box_n = 0;
-    if (B->shared_box && any_box) {
-        for (int64_t k = 0; k < nmeta; ++k) {
-            if (h->h_kind[k] != BLP_KIND_HYPERBOX) continue;
-            if (sp.box_n == 0) sp.box_n = h->h_n[k];
-            if (h->h_n[k] != sp.box_n)
-                return fail(h, BLP_ERR_ARG, "LP %lld: a shared box needs every hyperbox LP to have n = %d",
-                            (long long)k, sp.box_n);
-        }
-    }
-    if (!uni) {
-        h->h_a_off.resize(K);
-        h->h_row_off.resize(K);
-        h->h_col_off.resize(K);
-        int64_t ao = 0, ro = 0, co = 0;
-        for (int64_t k = 0; k < K; ++k) {
-            h->h_a_off[k] = B->a_off ? B->a_off[k] : ao;
-            h->h_row_off[k] = B->row_off ? B->row_off[k] : ro;
-            h->h_col_off[k] = B->col_off ? B->col_off[k] : co;
-            if (h->h_a_off[k] < 0 || h->h_row_off[k] < 0 || h->h_col_off[k] < 0)
-                return fail(h, BLP_ERR_ARG, "LP %lld: negative offset", (long long)k);
-            ao += (int64_t)h->h_m[k] * h->h_n[k];
-            ro += h->h_m[k];
-            co += h->h_n[k];
-        }
-        tot_a = tot_m = tot_n = 0;
-        for (int64_t k = 0; k < K; ++k) {
-            tot_a = std::max(tot_a, h->h_a_off[k] + (int64_t)h->h_m[k] * h->h_n[k]);
-            tot_m = std::max(tot_m, h->h_row_off[k] + h->h_m[k]);
-            tot_n = std::max(tot_n, h->h_col_off[k] + h->h_n[k]);
-        }
-    }
+    PlanIn in;
+    in.count = K;
+    in.uniform = uni;
+    in.shared_box = B->shared_box != 0;
+    in.m = B->m;
+    in.n = B->n;
+    in.kind = B->kind;
+    in.a_off = B->a_off;
+    in.row_off = B->row_off;
+    in.col_off = B->col_off;
+    in.has_A = B->A;
+    in.has_b = B->b;
+    in.has_sense = B->sense;
+    in.has_c = B->c;
+    in.has_l = B->l;
+    in.has_u = B->u;
+    in.variants = shapes.data();
+    in.nreg = h->nreg;
+    in.force = h->opt.variant;
+    in.remap_streams = remap_streams;
+    in.stream_all = stream_all;
+    Plan& pl = h->plan;
+    if (plan_batch(in, pl) != PLAN_OK) return fail(h, (blp_error)pl.code, "%s", pl.msg.c_str());
+    const bool any_simplex = pl.any_simplex, any_box = pl.any_box;
+    const int64_t n_box = pl.n_box, tot_m = pl.tot_m, tot_n = pl.tot_n, max_slot = pl.max_slot;
+    const int64_t n_may_stream = pl.n_may_stream;
+    const int max_m = pl.max_m, max_cols = pl.max_cols;
+    sp.gm_deep = pl.gm_deep;
+    sp.box_n = pl.box_n;
 
     // ---- outputs
     blp_outputs o{};
@@ -558,21 +491,21 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P = KParams{};
     P.count = K;
     P.uniform = uni ? 1 : 0;
-    P.um = h->h_m[0];
-    P.un = h->h_n[0];
-    P.ukind = h->h_kind[0];
+    P.um = h->plan.m[0];
+    P.un = h->plan.n[0];
+    P.ukind = h->plan.kind[0];
     if (!uni) {
         const size_t bytes = (size_t)K * (3 * sizeof(int32_t) + 3 * sizeof(int64_t));
         char* base = nullptr;
         BUF_TRY(h, arena, h->meta, bytes, base);
         int64_t* offs = reinterpret_cast<int64_t*>(base);
         int32_t* ints = reinterpret_cast<int32_t*>(base + (size_t)K * 3 * sizeof(int64_t));
-        HIP_TRY(h, hipMemcpyAsync(offs, h->h_a_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(offs + K, h->h_row_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(offs + 2 * K, h->h_col_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(ints, h->h_m.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(ints + K, h->h_n.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(h, hipMemcpyAsync(ints + 2 * K, h->h_kind.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(offs, pl.a_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(offs + K, pl.row_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(offs + 2 * K, pl.col_off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ints, pl.m.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ints + K, pl.n.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ints + 2 * K, pl.kind.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
         P.a_off = offs;
         P.row_off = offs + K;
         P.col_off = offs + 2 * K;
@@ -634,7 +567,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         sp.maybe[h->opt.variant] = 1;
     } else if (h->opt.variant == -1 && any_simplex) {
         if (uni) {
-            const int m = h->h_m[0], n = h->h_n[0];
+            const int m = h->plan.m[0], n = h->plan.n[0];
             for (int nart = 0; nart <= m; ++nart) {
                 int best = -1;
                 long barea = -1;
@@ -860,7 +793,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
             const unsigned char* c = static_cast<const unsigned char*>(p);
             for (size_t i = 0; i < n; ++i) f = (f ^ c[i]) * 1099511628211ull;
         };
-        mix(h->h_kind.data(), h->h_kind.size() * sizeof(int32_t));
+        mix(h->plan.kind.data(), h->plan.kind.size() * sizeof(int32_t));
         g.push_back(f);
     }
     return g;
@@ -900,44 +833,33 @@ static blp_error enqueue_eager(blp_handle h, SolvePlan& sp, hipStream_t s) {
 // and then sized exactly, so the call never holds more than S.
 static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outputs* out, hipStream_t s) {
     const int64_t K = B->count;
-    if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
     const bool uni = B->uniform != 0;
-    const int64_t nmeta = uni ? 1 : K;
     const uint64_t limit = h->opt.mem_limit;
-    std::vector<int64_t> ao, ro, co;  // packed offsets for NULL offset arrays
-    int64_t tot_m = 0, tot_n = 0, max_slot = 0;
-    bool any_simplex = false;
-    {
-        int64_t a = 0, r = 0, c = 0;
-        if (!uni) {
-            ao.resize(K);
-            ro.resize(K);
-            co.resize(K);
-        }
-        for (int64_t k = 0; k < nmeta; ++k) {
-            const int m = B->m[k], n = B->n[k];
-            if (m < 0 || n < 0 || m > kMaxM || n > kMaxCols)
-                return fail(h, BLP_ERR_ARG, "LP %lld: size out of range", (long long)k);
-            if (B->kind[k] == BLP_KIND_SIMPLEX) {
-                any_simplex = true;
-                max_slot = std::max<int64_t>(max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
-            }
-            if (!uni) {
-                ao[k] = B->a_off ? B->a_off[k] : a;
-                ro[k] = B->row_off ? B->row_off[k] : r;
-                co[k] = B->col_off ? B->col_off[k] : c;
-                tot_m = std::max(tot_m, ro[k] + m);
-                tot_n = std::max(tot_n, co[k] + n);
-                a += (int64_t)m * n;
-                r += m;
-                c += n;
-            }
-        }
-        if (uni) {
-            tot_m = K * (int64_t)B->m[0];
-            tot_n = K * (int64_t)B->n[0];
-        }
-    }
+    // the whole batch's extents and largest streaming slot (arguments are
+    // checked again for each chunk by prepare)
+    PlanIn in;
+    in.count = K;
+    in.uniform = uni;
+    in.shared_box = B->shared_box != 0;
+    in.m = B->m;
+    in.n = B->n;
+    in.kind = B->kind;
+    in.a_off = B->a_off;
+    in.row_off = B->row_off;
+    in.col_off = B->col_off;
+    in.has_A = B->A;
+    in.has_b = B->b;
+    in.has_sense = B->sense;
+    in.has_c = B->c;
+    in.has_l = B->l;
+    in.has_u = B->u;
+    Plan whole;
+    if (plan_batch(in, whole) != PLAN_OK) return fail(h, (blp_error)whole.code, "%s", whole.msg.c_str());
+    const int64_t tot_m = whole.tot_m, tot_n = whole.tot_n, max_slot = whole.max_slot;
+    const bool any_simplex = whole.any_simplex;
+    const std::vector<int64_t>& ao = whole.a_off;
+    const std::vector<int64_t>& ro = whole.row_off;
+    const std::vector<int64_t>& co = whole.col_off;
     const bool own_st = !out || !out->status, own_it = !out || !out->iters, own_ob = !out || !out->obj;
     const bool own_x = !out || !out->x, own_y = !out || !out->y;
     const size_t out_bytes = (own_st ? 4 * (size_t)K : 0) + (own_it ? 4 * (size_t)K : 0) +
@@ -947,12 +869,12 @@ static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outpu
     const size_t slot = any_simplex ? sizeof(double) * (size_t)max_slot : 0;
     const size_t per_lp = uni ? 8 : 48;
     const size_t fixed = out_bytes + counters + slot;
-    if (fixed + per_lp > limit)
+    const int64_t cap = chunk_capacity(limit, fixed, per_lp, K);
+    if (cap < 1)
         return fail(h, BLP_ERR_NOMEM,
                     "mem_limit of %llu bytes: %zu bytes of results, %zu of bin counters and a %zu-byte workspace "
                     "slot leave no room for one LP (%zu bytes)",
                     (unsigned long long)limit, out_bytes, counters, slot, per_lp);
-    const int64_t cap = (int64_t)std::min<uint64_t>((limit - fixed) / per_lp, (uint64_t)K);
     // the buffers are sized for this call alone
     for (DevBuf* b : {&h->meta, &h->counters, &h->binid, &h->list, &h->olist, &h->ws, &h->own_status, &h->own_iters,
                       &h->own_obj, &h->own_x, &h->own_y})
@@ -996,7 +918,7 @@ static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outpu
             sub.kind = B->kind + k0;
             sub.a_off = ao.data() + k0;
             sub.row_off = ro.data() + k0;
-            sub.col_off = co.data() + k0;
+            sub.col_off = co.data() + k0;  // (the whole batch's plan outlives the loop)
         }
         const size_t ws_budget = (size_t)(limit - out_bytes - counters - per_lp * (size_t)kc);
         blp_error e = prepare(h, &sub, &os, s, sp, false, nullptr, std::max<size_t>(ws_budget, 1));
@@ -1013,14 +935,7 @@ static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outpu
     h->last.obj = o.obj;
     h->last.x = o.x;
     h->last.y = o.y;
-    h->h_m.assign(B->m, B->m + nmeta);
-    h->h_n.assign(B->n, B->n + nmeta);
-    h->h_kind.assign(B->kind, B->kind + nmeta);
-    if (!uni) {
-        h->h_a_off = ao;
-        h->h_row_off = ro;
-        h->h_col_off = co;
-    }
+    h->plan = std::move(whole);
     h->chunked = nchunks > 1;
     return BLP_SUCCESS;
 }
@@ -1245,6 +1160,7 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
     }
     struct Range { int64_t lo = INT64_MAX, hi = 0; };
     std::vector<int64_t> order;
+    std::vector<CopyRun> runs;
     for (int32_t ch = 0; ch < chunks; ++ch) {
         const int64_t k0 = K * ch / chunks, k1 = K * (ch + 1) / chunks, Kc = k1 - k0;
         const int slot = ch & 1;
@@ -1328,33 +1244,11 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
         HIP_TRY(h, hipMemcpyAsync(out->iters + k0, oit, sizeof(int32_t) * Kc, hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipMemcpyAsync(out->obj + k0, oobj, sizeof(double) * Kc, hipMemcpyDeviceToHost, s));
         for (int pass = 0; pass < 2; ++pass) {
-            const std::vector<int64_t>& off = pass == 0 ? co : ro;
-            const std::vector<int32_t>& len = pass == 0 ? n : m;
-            const int64_t lo = pass == 0 ? rc.lo : rr.lo;
+            copy_runs(pass == 0 ? co : ro, pass == 0 ? n : m, k0, k1, pass == 0 ? rc.lo : rr.lo, order, runs);
             double* dst = pass == 0 ? out->x : out->y;
             const double* src = pass == 0 ? ox : oy;
-            order.resize((size_t)Kc);
-            for (int64_t k = k0; k < k1; ++k) order[(size_t)(k - k0)] = k;
-            if (!std::is_sorted(order.begin(), order.end(),
-                                [&](int64_t a, int64_t b) { return off[a] < off[b]; }))
-                std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return off[a] < off[b]; });
-            int64_t run_lo = -1, run_hi = -1;
-            for (size_t q = 0; q <= order.size(); ++q) {
-                const bool last = q == order.size();
-                const int64_t k = last ? 0 : order[q];
-                if (!last && len[k] == 0) continue;
-                if (!last && off[k] == run_hi) {
-                    run_hi += len[k];
-                    continue;
-                }
-                if (run_hi > run_lo)
-                    HIP_TRY(h, hipMemcpyAsync(dst + run_lo, src + (run_lo - lo), sizeof(double) * (run_hi - run_lo),
-                                              hipMemcpyDeviceToHost, s));
-                if (!last) {
-                    run_lo = off[k];
-                    run_hi = off[k] + len[k];
-                }
-            }
+            for (const CopyRun& r : runs)
+                HIP_TRY(h, hipMemcpyAsync(dst + r.dst, src + r.src, sizeof(double) * r.len, hipMemcpyDeviceToHost, s));
         }
     }
     for (int i = 0; i < 2; ++i) HIP_TRY(h, hipStreamSynchronize(h->pipe[i]));
@@ -1363,15 +1257,15 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* B, const blp_outpu
 
 static void lp_offsets(blp_handle h, int64_t k, int* m, int* n, int64_t* ro, int64_t* co) {
     if (h->uniform) {
-        *m = h->h_m[0];
-        *n = h->h_n[0];
+        *m = h->plan.m[0];
+        *n = h->plan.n[0];
         *ro = k * (int64_t)*m;
         *co = k * (int64_t)*n;
     } else {
-        *m = h->h_m[k];
-        *n = h->h_n[k];
-        *ro = h->h_row_off[k];
-        *co = h->h_col_off[k];
+        *m = h->plan.m[k];
+        *n = h->plan.n[k];
+        *ro = h->plan.row_off[k];
+        *co = h->plan.col_off[k];
     }
 }
 
@@ -1411,8 +1305,8 @@ blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, 
         tot_n = std::max(tot_n, co + n);
     }
     if (h->uniform) {
-        tot_m = K * (int64_t)h->h_m[0];
-        tot_n = K * (int64_t)h->h_n[0];
+        tot_m = K * (int64_t)h->plan.m[0];
+        tot_n = K * (int64_t)h->plan.n[0];
     }
     const KParams& P = h->last;
     if (on_device) {
