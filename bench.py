@@ -30,6 +30,7 @@ PEAK_LDS_GBS = 78643.2    # 256 CUs x 128 B/clk x 2.4 GHz
 METRIC = "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj relerr\u22641e-9"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel__type1_m100_n100_K50000.json")
 KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_blk.hpp",
+                  "paper_1609_08114_amd/csrc/simplex_cols.hpp", "paper_1609_08114_amd/csrc/simplex_lane.hpp",
                   "paper_1609_08114_amd/csrc/simplex_common.hpp", "paper_1609_08114_amd/csrc/blp_kernels.hpp",
                   "paper_1609_08114_amd/csrc/variants.hpp"]
 
@@ -93,6 +94,55 @@ def time_solver(blp, torch, db, steps, warmup, profile=True, warm_ms=0.0, step_t
     return (t1 - t0) * 1e3 / steps, kms, out, bins
 
 
+TIMER_LIB = os.path.join(ROOT, "paper_1609_08114_amd", "libblp_timers.so")
+
+
+def _timer_child(K: int) -> None:
+    """Run in a child process with BLP_LIBRARY naming the phase-timer build:
+    one solve of the headline batch; closing the handle prints the phase
+    cycle counters (summed over the LP's first wave, per LP and per pivot)."""
+    import torch
+
+    import lpgen
+    import paper_1609_08114_amd as blp
+    db = blp.DeviceBatch.from_host(lpgen.config(2, range(K)))
+    s = blp.Solver()
+    s.solve(db)
+    torch.cuda.synchronize()
+    s.close()
+
+
+def phase_timers(K: int) -> dict | None:
+    """Per-phase cycles of the headline solve from the phase-timer build (a
+    child process), or None if that build is absent.  For the column-split
+    kernel the four pivot phases are: candidate (the wave's Step 1, column
+    publication and Step 2), exchange (candidate record, the barrier, the
+    winner), pivot row (publication and division) and update (mirrors and
+    the rank-1 update of the tile)."""
+    import re
+    import subprocess
+    if not os.path.exists(TIMER_LIB):
+        return None
+    env = dict(os.environ, BLP_LIBRARY=TIMER_LIB)
+    r = subprocess.run([sys.executable, "-c", f"import bench; bench._timer_child({K})"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    m = re.search(r"\[blp timers\] LPs (\d+) pivots (\d+) \| cycles per LP: load ([\d.]+) extract ([\d.]+) \| "
+                  r"per pivot: price ([\d.]+) pubcol ([\d.]+) ratio ([\d.]+) pivot ([\d.]+)", r.stderr)
+    if r.returncode != 0 or not m:
+        log(f"phase timers: no counters (rc {r.returncode}): {r.stderr[-400:]}")
+        return None
+    lps, piv = int(m.group(1)), int(m.group(2))
+    load, extract, cand, exch, prow, upd = (float(m.group(i)) for i in range(3, 9))
+    per_pivot = cand + exch + prow + upd
+    per_lp = load + extract + per_pivot * piv / max(lps, 1)
+    return {"lps": lps, "pivots": piv, "unit": "cycles of one wave (s_memtime), per LP and per pivot",
+            "per_lp": {"load": round(load), "extract": round(extract)},
+            "per_pivot": {"candidate": round(cand), "exchange": round(exch), "pivot_row": round(prow),
+                          "update": round(upd)},
+            "update_share_of_pivot": round(upd / per_pivot, 4) if per_pivot > 0 else None,
+            "pivot_loop_share_of_lp": round(per_pivot * piv / max(lps, 1) / per_lp, 4) if per_lp > 0 else None}
+
+
 def rate_one_per_launch(blp, torch, lpgen, cfg, ids, **kw):
     hb = lpgen.config(cfg, ids) if not isinstance(cfg, tuple) else lpgen.config(cfg[0], ids, part=cfg[1])
     db = blp.DeviceBatch.from_host(hb)
@@ -118,9 +168,17 @@ def main():
     ap.add_argument("--counter-pass", action="store_true",
                     help="only a 1 GiB device copy followed by one persistent solve of the batch "
                          "(the workload of the HBM-counter runs)")
+    ap.add_argument("--counter-workload", default="2", choices=["2", "3", "box5", "box28"],
+                    help="--counter-pass: the headline batch (2), workload 3 at its 10,000 LPs, or the "
+                         "4,000,000 n=5 / 6,000,000 n=28 hyperbox batches of workload 5")
+    ap.add_argument("--counter-table", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the HBM bytes of every kernel of two counter runs (scaled by the copy), then exit")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(*args.traffic_from, batch=args.batch)
+        return
+    if args.counter_table:
+        print(json.dumps(counter_table(*args.counter_table), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch shards across GPUs "
@@ -134,7 +192,7 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
 
     if args.counter_pass:
-        counter_pass(blp, torch, lpgen, args.batch)
+        counter_pass(blp, torch, lpgen, args.batch, args.counter_workload)
         return
 
     # ------------------------------------------------------------ main line
@@ -182,6 +240,12 @@ def main():
                 "context_full_tableau_frac": round(full / (dom_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
                 "hbm_input_bytes": input_bytes,
                 "hbm_frac_of_input_read": round(input_bytes / (dom_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+    # per-phase cycles of the same solve (phase-timer build, child process)
+    timers = phase_timers(K)
+    if timers:
+        roofline["phase_cycles"] = timers
+        log(f"phase timers: {timers}")
 
     # ------------------------------------------------- one LP per launch
     S = min(args.one_per_launch_sample, K)
@@ -308,20 +372,41 @@ def rate_host_resident(blp, torch, hb, ref_obj, steps=3):
             "obj_identical_to_resident": same}
 
 
+def _read_counter(path, counter):
+    import csv
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def counter_table(fetch_csv: str, write_csv: str) -> dict:
+    """HBM bytes per dispatch of every kernel of a FETCH_SIZE and a
+    WRITE_SIZE run, each scaled so that the run's 1 GiB device copy reads
+    and writes 1 GiB."""
+    f = _read_counter(fetch_csv, "FETCH_SIZE")
+    w = _read_counter(write_csv, "WRITE_SIZE")
+    copy = next(k for k in f if "copyBuffer" in k or "copy" in k.lower())
+    kib = float(1 << 20)
+    ff, fw = kib / f[copy][0], kib / w[copy][0]
+    out = {"fetch_factor": round(ff, 4), "write_factor": round(fw, 4), "kernels": {}}
+    for k in f:
+        if k == copy:
+            continue
+        fb = [v * ff * 1024.0 for v in f[k]]
+        wb = [v * fw * 1024.0 for v in w.get(k, [0.0])]
+        out["kernels"][k.split("(")[0][:120]] = {"dispatches": len(fb), "fetch_bytes_max": max(fb),
+                                                "write_bytes_max": max(wb)}
+    return out
+
+
 def write_traffic(fetch_csv: str, write_csv: str, batch: int) -> None:
     """HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
     runs of --counter-pass, each counter scaled by what it reads for the
     1 GiB device copy of the same run."""
-    import csv
-
-    def read(path, counter):
-        vals = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == counter:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return vals
-    f = read(fetch_csv, "FETCH_SIZE")
-    w = read(write_csv, "WRITE_SIZE")
+    f = _read_counter(fetch_csv, "FETCH_SIZE")
+    w = _read_counter(write_csv, "WRITE_SIZE")
     copy = next(k for k in f if "copyBuffer" in k or "copy" in k.lower())
     kib = float(1 << 20)  # the copy moves 1 GiB each way
     ff, fw = kib / f[copy][0], kib / w[copy][0]
@@ -337,22 +422,30 @@ def write_traffic(fetch_csv: str, write_csv: str, batch: int) -> None:
     print(json.dumps(out))
 
 
-def counter_pass(blp, torch, lpgen, K):
+def counter_pass(blp, torch, lpgen, K, workload="2"):
     """The workload of the HBM byte-counter runs: one plain device copy of
     1 GiB (the calibration of FETCH_SIZE/WRITE_SIZE) and one persistent solve
-    of the K-LP batch."""
+    of the K-LP headline batch, of workload 3 (10,000 LPs) or of a full
+    hyperbox batch of workload 5."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    hb = lpgen.config(2, range(K))
+    del src, dst
+    if workload == "3":
+        hb, K = lpgen.config(3, range(10_000)), 10_000
+    elif workload.startswith("box"):
+        K = 4_000_000 if workload == "box5" else 6_000_000
+        hb = lpgen.config(5, range(K), part=workload)
+    else:
+        hb = lpgen.config(2, range(K))
     db = blp.DeviceBatch.from_host(hb)
     s = blp.Solver()
     s.solve(db)
     torch.cuda.synchronize()
     s.close()
-    log(f"counter pass done: copy of {src.numel() * 8} bytes, one solve of {K} LPs")
+    log(f"counter pass done: copy of {1 << 30} bytes, one solve of {K} LPs (workload {workload})")
 
 
 def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:

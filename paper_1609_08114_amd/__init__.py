@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libblp.so")
+# BLP_LIBRARY may name another build of the same library (the phase-timer
+# build); there is no fallback when it is missing
+LIB_PATH = os.environ.get("BLP_LIBRARY") or os.path.join(HERE, "libblp.so")
 
 BLP_LE, BLP_GE = 0, 1
 BLP_KIND_SIMPLEX, BLP_KIND_HYPERBOX = 0, 1

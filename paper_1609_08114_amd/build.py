@@ -16,8 +16,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblp.so")
+# the same library with in-kernel phase cycle counters (-DBLP_PHASE_TIMERS),
+# for the per-phase breakdown of a solve; never the default
+LIB_TIMERS = os.path.join(HERE, "libblp_timers.so")
+BUILD_TIMERS = os.path.join(HERE, "_build_timers")
 SOURCES = ["simplex_reg.hip", "simplex_gm.hip", "aux_kernels.hip", "blp_runtime.cpp"]
-HEADERS = ["blp_kernels.hpp", "simplex_common.hpp", "simplex_blk.hpp", "simplex_lane.hpp", "variants.hpp",
+HEADERS = ["blp_kernels.hpp", "simplex_common.hpp", "simplex_blk.hpp", "simplex_lane.hpp", "simplex_cols.hpp", "variants.hpp",
            "aux_kernels.hpp"]
 
 
@@ -69,6 +73,12 @@ def build(verbose: bool = False, jobs: int = 4, out: str = LIB, build_dir: str =
     return out
 
 
+def build_timers(verbose: bool = False) -> str:
+    """The phase-timer build (same sources, -DBLP_PHASE_TIMERS)."""
+    return build(verbose=verbose, out=LIB_TIMERS, build_dir=BUILD_TIMERS, extra=("-DBLP_PHASE_TIMERS",))
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_timers(verbose=True)
     sys.exit(0)

@@ -42,12 +42,17 @@ __device__ __forceinline__ int art_count(const ArtLoads& a, int m, int i0, int l
 __device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, int nart) {
     const int rows = L.m + 2, cols = L.n + nart + 1;
     int bin = vt.nreg;  // streaming kernel
+    // a variant for LPs without artificial rows under the largest-
+    // coefficient rule takes only those
+    const bool t1 = nart == 0 && vt.lpc;
     if (vt.force >= 0) {
-        if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols) bin = vt.force;
+        if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols &&
+            (t1 || !vt.type1[vt.force]))
+            bin = vt.force;
     } else if (vt.force == -1) {
         long best = -1;
         for (int v = 0; v < vt.nreg; ++v) {
-            if (vt.rows[v] >= rows && vt.cols[v] >= cols) {
+            if (vt.rows[v] >= rows && vt.cols[v] >= cols && (t1 || !vt.type1[v])) {
                 const long area = (long)vt.rows[v] * vt.cols[v];
                 if (best < 0 || area < best) {
                     best = area;
@@ -55,7 +60,10 @@ __device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, in
                 }
             }
         }
-        if (bin < vt.nreg) bin = vt.remap[bin];
+        if (bin < vt.nreg) {
+            const int r = vt.remap[bin];
+            if (r >= vt.nreg || t1 || !vt.type1[r]) bin = r;
+        }
     }
     return bin;
 }

@@ -20,6 +20,8 @@ struct VariantTable {
     int rows[kMaxVariants];
     int cols[kMaxVariants];
     int remap[kMaxVariants];  // autotuned replacement of each variant (nreg = streaming)
+    int type1[kMaxVariants];  // 1: the variant takes only LPs without artificial rows under LPC
+    int lpc;                  // 1: the largest-coefficient rule (else the random rule)
 };
 
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);

@@ -176,6 +176,14 @@ struct blp_handle_s {
 
 static blp_error fail(blp_handle h, blp_error code, const char* fmt, ...);
 
+// Can variant w (nreg: the streaming kernel) take every LP that the
+// scheduler sends to variant v?
+static bool can_replace(blp_handle h, int w, int v) {
+    if (w >= h->nreg) return true;
+    return h->variants[w].max_rows >= h->variants[v].max_rows && h->variants[w].max_cols >= h->variants[v].max_cols &&
+           (!h->variants[w].type1_only || h->variants[v].type1_only);
+}
+
 // Persistent grid of register variant v for `lps` LPs: its occupancy-sized
 // worker count, but no more workgroups than the LPs fill.
 static int reg_grid(blp_handle h, int v, int64_t lps) {
@@ -427,7 +435,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     std::vector<VariantShape> shapes((size_t)h->nreg);
     bool remap_streams = false;
     for (int v = 0; v < h->nreg; ++v) {
-        shapes[v] = {h->variants[v].max_rows, h->variants[v].max_cols};
+        shapes[v] = {h->variants[v].max_rows, h->variants[v].max_cols, h->variants[v].type1_only};
         remap_streams |= h->remap[v] >= h->nreg;
     }
     PlanIn in;
@@ -450,6 +458,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     in.nreg = h->nreg;
     in.force = h->opt.variant;
     in.remap_streams = remap_streams;
+    in.lpc = h->opt.pivot_rule == BLP_RULE_LPC;
     in.stream_all = stream_all;
     Plan& pl = h->plan;
     if (plan_batch(in, pl) != PLAN_OK) return fail(h, (blp_error)pl.code, "%s", pl.msg.c_str());
@@ -569,17 +578,23 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
         if (uni) {
             const int m = h->plan.m[0], n = h->plan.n[0];
             for (int nart = 0; nart <= m; ++nart) {
+                const bool t1 = nart == 0 && h->opt.pivot_rule == BLP_RULE_LPC;
                 int best = -1;
                 long barea = -1;
                 for (int v = 0; v < nreg; ++v)
-                    if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + nart + 1) {
+                    if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + nart + 1 &&
+                        (t1 || !h->variants[v].type1_only)) {
                         long a = (long)h->variants[v].max_rows * h->variants[v].max_cols;
                         if (barea < 0 || a < barea) {
                             barea = a;
                             best = v;
                         }
                     }
-                if (best >= 0 && h->remap[best] < nreg) sp.maybe[h->remap[best]] = 1;
+                if (best >= 0) {
+                    const int r = h->remap[best];
+                    const int to = (r >= nreg || t1 || !h->variants[r].type1_only) ? r : best;
+                    if (to < nreg) sp.maybe[to] = 1;
+                }
             }
         } else {
             std::fill(sp.maybe.begin(), sp.maybe.end(), 1);
@@ -629,7 +644,9 @@ static VariantTable variant_table(blp_handle h) {
         vt.rows[v] = h->variants[v].max_rows;
         vt.cols[v] = h->variants[v].max_cols;
         vt.remap[v] = h->remap[v];
+        vt.type1[v] = h->variants[v].type1_only;
     }
+    vt.lpc = h->opt.pivot_rule == BLP_RULE_LPC;
     return vt;
 }
 
@@ -1087,12 +1104,14 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         int v = -1;
         if (h->opt.variant >= 0) {
             v = h->opt.variant;
-            if (h->variants[v].max_rows < m + 2 || h->variants[v].max_cols < n + nart + 1)
+            if (h->variants[v].max_rows < m + 2 || h->variants[v].max_cols < n + nart + 1 ||
+                (h->variants[v].type1_only && (nart > 0 || h->opt.pivot_rule != BLP_RULE_LPC)))
                 return fail(h, BLP_ERR_TOO_LARGE, "variant %s cannot hold the shared constraints",
                             h->variants[v].name);
         }
         for (int i = 0; i < h->nreg && v < 0; ++i)
-            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols) v = i;
+            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols && !h->variants[i].type1_only)
+                v = i;
         if (v < 0) return fail(h, BLP_ERR_STATE, "no register variant of the shared tile shape");
         P.shared_in = 1;
         HIP_TRY(h, launch_reset(P.bin_head, 1, s));
@@ -1409,9 +1428,9 @@ blp_error blp_load_tuning(blp_handle h, const char* path) {
         const int w = index_of(txt.substr(p + key.size(), q - p - key.size()));
         if (w < 0) return fail(h, BLP_ERR_ARG, "unknown variant in %s", path);
         // a replacement must hold every LP of the original bin
-        if (w < h->nreg && (h->variants[w].max_rows < h->variants[v].max_rows ||
-                            h->variants[w].max_cols < h->variants[v].max_cols))
-            return fail(h, BLP_ERR_ARG, "%s maps %s to a smaller variant", path, h->variants[v].name);
+        if (!can_replace(h, w, v))
+            return fail(h, BLP_ERR_ARG, "%s maps %s to a variant that cannot hold its LPs", path,
+                        h->variants[v].name);
         remap[v] = w;
     }
     for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = remap[v];
@@ -1481,9 +1500,7 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         float best_ms = -1.f;
         int best = v;
         for (int w = 0; w <= nreg; ++w) {
-            if (w < nreg && (h->variants[w].max_rows < h->variants[v].max_rows ||
-                             h->variants[w].max_cols < h->variants[v].max_cols))
-                continue;
+            if (!can_replace(h, w, v)) continue;
             float ms = 0.f;
             for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
                 HIP_TRY(h, launch_reset(tb + 2, 1, s));

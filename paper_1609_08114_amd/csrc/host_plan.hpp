@@ -22,6 +22,7 @@ enum { PLAN_OK = 0, PLAN_ERR_ARG = 1, PLAN_ERR_NOMEM = 2, PLAN_ERR_TOO_LARGE = 5
 
 struct VariantShape {
     int rows, cols;  // largest tableau (rows incl. objective rows, columns incl. rhs)
+    int type1 = 0;   // 1: takes only LPs without artificial rows under the largest-coefficient rule
 };
 
 struct PlanIn {
@@ -35,6 +36,7 @@ struct PlanIn {
     int force = -1;              // -1 automatic, -2 streaming only, >= 0 one variant
     bool remap_streams = false;  // the autotuner sends some register bin to the streaming kernel
     bool stream_all = false;     // size the workspace as if every simplex LP could stream
+    bool lpc = true;             // the largest-coefficient rule (type-1-only variants take LPs)
 };
 
 struct Plan {
@@ -84,7 +86,8 @@ inline int plan_batch(const PlanIn& in, Plan& p) {
         if (in.force == -2) return true;
         for (int v = 0; v < in.nreg; ++v) {
             if (in.force >= 0 && v != in.force) continue;
-            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + 1) return false;
+            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + 1 && (in.lpc || !in.variants[v].type1))
+                return false;
         }
         return true;
     };
@@ -93,7 +96,7 @@ inline int plan_batch(const PlanIn& in, Plan& p) {
         if (in.stream_all || in.force == -2 || in.remap_streams) return false;
         for (int v = 0; v < in.nreg; ++v) {
             if (in.force >= 0 && v != in.force) continue;
-            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + m + 1) return true;
+            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + m + 1 && !in.variants[v].type1) return true;
         }
         return false;
     };

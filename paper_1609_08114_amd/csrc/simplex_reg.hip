@@ -27,6 +27,7 @@
 #include "simplex_blk.hpp"
 #include "simplex_common.hpp"
 #include "simplex_lane.hpp"
+#include "simplex_cols.hpp"
 #include "variants.hpp"
 
 namespace blp {
@@ -402,6 +403,19 @@ static const void* kernel_ptr_blk() {
     return reinterpret_cast<const void*>(&simplex_blk_kernel<NW, GC, RB, CB, WPE>);
 }
 
+// ROWS x COLS: the shape the variant claims (ROWS - 2 constraint rows and
+// COLS - 1 column slots), which its tile must hold
+template <int NW, int GCW, int RB, int CB, int WPE, int ROWS, int COLS>
+static hipError_t launch_cols(const KParams& P, int grid, hipStream_t s) {
+    static_assert(ROWS - 2 <= 64 / GCW * RB && COLS - 1 <= NW * GCW * CB, "column-split shape");
+    hipLaunchKernelGGL((simplex_cols_kernel<NW, GCW, RB, CB, WPE>), dim3(grid), dim3(NW * 64), 0, s, P);
+    return hipGetLastError();
+}
+template <int NW, int GCW, int RB, int CB, int WPE>
+static const void* kernel_ptr_cols() {
+    return reinterpret_cast<const void*>(&simplex_cols_kernel<NW, GCW, RB, CB, WPE>);
+}
+
 template <int R, int C, int NWV, int WPE>
 static hipError_t launch_lane(const KParams& P, int grid, hipStream_t s) {
     hipLaunchKernelGGL((simplex_lane_kernel<R, C, NWV, WPE>), dim3(grid), dim3(NWV * 64), 0, s, P);
@@ -428,12 +442,15 @@ void shared_shape(int* rows, int* cols) {
 
 #define BLP_BLK_VARIANT(NAME, NW, GC, RB, CB, WPE)                                                    \
     {NAME, (NW) * 64, (NW) * 64 / (GC) * (RB), (GC) * (CB), &launch_blk<NW, GC, RB, CB, WPE>, \
-     &kernel_ptr_blk<NW, GC, RB, CB, WPE>, 1},
+     &kernel_ptr_blk<NW, GC, RB, CB, WPE>, 1, 0},
 #define BLP_REG_VARIANT(NAME, NW, TC, CT, WPE)                                                                  \
     {NAME, (NW) * 64, (NW) * 64 / (TC), (TC) * (CT), &launch_reg<NW, TC, CT, WPE>, &kernel_ptr<NW, TC, CT, WPE>, \
-     1},
+     1, 0},
+#define BLP_COLS_VARIANT(NAME, NW, GCW, RB, CB, WPE, ROWS, COLS)                                  \
+    {NAME, (NW) * 64, ROWS, COLS, &launch_cols<NW, GCW, RB, CB, WPE, ROWS, COLS>,                 \
+     &kernel_ptr_cols<NW, GCW, RB, CB, WPE>, 1, 1},
 #define BLP_LANE_VARIANT(NAME, R, C, NWV, WPE) \
-    {NAME, (NWV) * 64, R, C, &launch_lane<R, C, NWV, WPE>, &kernel_ptr_lane<R, C, NWV, WPE>, (NWV) * 64},
+    {NAME, (NWV) * 64, R, C, &launch_lane<R, C, NWV, WPE>, &kernel_ptr_lane<R, C, NWV, WPE>, (NWV) * 64, 0},
 
 const RegVariant* reg_variants(int* count) {
     static const RegVariant table[] = {BLP_REG_VARIANT_LIST};

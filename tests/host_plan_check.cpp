@@ -25,7 +25,7 @@ static int failures = 0;
         }                                                 \
     } while (0)
 
-static const VariantShape kShapes[] = {{8, 8}, {7, 11}, {8, 8}, {16, 16}, {32, 32}, {64, 64},
+static const VariantShape kShapes[] = {{8, 8}, {7, 11}, {8, 8}, {16, 16}, {32, 32}, {64, 64}, {112, 112, 1},
                                        {112, 112}, {128, 112}, {128, 128}, {160, 160}};
 
 int main() {
