@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BLP_ABI_VERSION 2
+#define BLP_ABI_VERSION 3
 
 typedef struct blp_handle_s* blp_handle;
 
@@ -185,6 +185,31 @@ blp_error blp_create(blp_handle* out, const blp_options* opt);
  * The handle remembers the batch and output pointers for blp_backward and
  * blp_get_solution*, until the next solve. */
 blp_error blp_solve_batch(blp_handle h, const blp_batch* batch, const blp_outputs* out, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as blp_solve_batch, with every output buffer required (all five,
+ * DEVICE memory) and everything else the solve needs on the device -- batch
+ * metadata, work lists, bin counters, the streaming kernel's workspace --
+ * taken from a static scratch array of BLP_STATIC_SCRATCH_BYTES per GPU
+ * (held by every GPU the library runs on until the process ends).  Calls no
+ * hipMalloc, hipFree or other allocating routine; launches eagerly on the
+ * stream (the handle's graph and mem_limit options do not apply).  A batch
+ * whose metadata and work lists (8 bytes per LP for a uniform batch, 48
+ * otherwise) do not fit, or that leaves no room for one streaming workspace
+ * slot when it needs one, fails with BLP_ERR_TOO_LARGE before any launch;
+ * the streaming kernel runs as many workgroups as the remaining scratch
+ * holds slots for (fewer workgroups, the same results).  Every call on a
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (on
+ * different streams or handles) race and must be ordered by the caller, and
+ * blp_backward and blp_get_solution* after this call read the batch
+ * metadata from the scratch, so they must come before the next such call
+ * on the GPU. */
+#define BLP_STATIC_SCRATCH_BYTES (64ull << 20)
+blp_error blp_solve_batch_static(blp_handle h, const blp_batch* batch, const blp_outputs* out, void* hip_stream);
+
+/* BLP_STATIC_SCRATCH_BYTES as compiled into the library. */
+size_t blp_static_scratch_bytes(void);
 
 /* Host-resident batch with copy/compute overlap (the stream scheme of
  * Sec. 4.4).  Same batch description as blp_solve_batch except that the

@@ -32,7 +32,7 @@ ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR
 EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
            "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning",
-           "blp_solve_batch_host", "blp_solve_shared"]
+           "blp_solve_batch_host", "blp_solve_shared", "blp_solve_batch_static", "blp_static_scratch_bytes"]
 
 
 class blp_options(ctypes.Structure):
@@ -95,8 +95,11 @@ def lib() -> ctypes.CDLL:
         L.blp_tuning.argtypes = [vp, vp, P(i32)]
         L.blp_solve_batch_host.argtypes = [vp, P(blp_batch), P(blp_outputs), i32]
         L.blp_solve_shared.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp, P(blp_outputs), vp]
+        L.blp_solve_batch_static.argtypes = [vp, P(blp_batch), P(blp_outputs), vp]
+        L.blp_static_scratch_bytes.argtypes = []
+        L.blp_static_scratch_bytes.restype = ctypes.c_size_t
         for f in EXPORTS:
-            if f not in ("blp_abi_version", "blp_destroy", "blp_last_error"):
+            if f not in ("blp_abi_version", "blp_destroy", "blp_last_error", "blp_static_scratch_bytes"):
                 getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -132,6 +135,14 @@ def blp_last_error(h) -> str:
 def blp_solve_batch(h, batch: blp_batch, out: blp_outputs | None = None, stream: int | None = None) -> None:
     _check(h, lib().blp_solve_batch(h, ctypes.byref(batch), ctypes.byref(out) if out is not None else None,
                                     stream))
+
+
+def blp_solve_batch_static(h, batch: blp_batch, out: blp_outputs, stream: int | None = None) -> None:
+    _check(h, lib().blp_solve_batch_static(h, ctypes.byref(batch), ctypes.byref(out), stream))
+
+
+def blp_static_scratch_bytes() -> int:
+    return lib().blp_static_scratch_bytes()
 
 
 def blp_solve_batch_host(h, batch: blp_batch, out: blp_outputs, chunks: int = 0) -> None:

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,31 @@ struct Arena {
     }
 };
 
+// The allocation-free entry point's scratch: one copy of this array per
+// GPU, kept until the process ends.  Host code never uses the array's name
+// as a device address: each device's address is resolved once, with that
+// device current, by blp_create (scratch_ptr below).
+constexpr size_t kStaticScratchBytes = (size_t)BLP_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+hipError_t scratch_ptr(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct blp_handle_s {
@@ -86,6 +112,7 @@ struct blp_handle_s {
     int cu_count = 0;
     const RegVariant* variants = nullptr;
     int nreg = 0;
+    void* scratch = nullptr;  // this device's copy of the static scratch (allocation-free entry point)
     std::vector<int> reg_workers;  // persistent grid per variant
     int gm_occ = 1;
     // device buffers
@@ -309,6 +336,7 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
     // never by the allocation-free entry point.
     hipError_t ce = h->create_forks();
     if (ce == hipSuccess) ce = hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming);
+    if (ce == hipSuccess) ce = scratch_ptr(o.device, &h->scratch);
     if (ce == hipSuccess && h->opt.profile) ce = h->ensure_events(h->nreg + 3);
     if (ce != hipSuccess) {
         blp_destroy(h);
@@ -1021,6 +1049,45 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
     record_solve(h, sp, K);
     return BLP_SUCCESS;
 }
+
+// Allocation-free variant of blp_solve_batch: the batch metadata, work
+// lists, bin counters and streaming workspace come from this device's static
+// scratch; the caller passes every output.  Eager launches only (no graph,
+// no mem_limit chunking).  The streaming kernel gets as many workspace slots
+// as the scratch still holds after the rest.
+blp_error blp_solve_batch_static(blp_handle h, const blp_batch* B, const blp_outputs* out, void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (!B) return fail(h, BLP_ERR_ARG, "batch is NULL");
+    if (!out || !out->status || !out->iters || !out->obj || !out->x || !out->y)
+        return fail(h, BLP_ERR_ARG, "all five output buffers are required");
+    if (B->count < 0 || B->count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    if (!h->scratch) return fail(h, BLP_ERR_STATE, "no static scratch on this device");
+    const int64_t K = B->count;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    h->solved = false;
+    if (K == 0) {
+        h->count = 0;
+        h->solved = true;
+        return BLP_SUCCESS;
+    }
+    HIP_TRY(h, begin_call(h, s));
+    Arena arena;
+    arena.base = static_cast<char*>(h->scratch);
+    arena.cap = kStaticScratchBytes;
+    SolvePlan sp;
+    blp_error e = prepare(h, B, out, s, sp, false, &arena);
+    if (e != BLP_SUCCESS) return e;
+    e = enqueue_eager(h, sp, s);
+    if (e != BLP_SUCCESS) return e;
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, end_call(h, s));
+    record_solve(h, sp, K);
+    return BLP_SUCCESS;
+}
+
+size_t blp_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 // ------------------------------------------------ host-resident pipeline
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
