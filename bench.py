@@ -273,6 +273,12 @@ def main():
     if not args.no_classes:
         shared = bench_shared(blp, torch, lpgen, oracle_check=not args.no_cpu)
 
+    # ------------------- captured launch sequences against eager launches
+    graphs = lanes = None
+    if not args.no_classes:
+        graphs = graph_replay(blp, torch, lpgen)
+        lanes = lane_scaling(blp, torch, lpgen)
+
     # -------------------- pivot rules: RPC (Sec. 4.2) against LPC, same batch
     rules = None
     if not args.no_classes:
@@ -336,6 +342,8 @@ def main():
         "layout_ablation": ablation,
         "shared_constraints": shared,
         "pivot_rules": rules,
+        "graph_replay": graphs,
+        "lane_kernel_scaling": lanes,
     }
     print(json.dumps(line), flush=True)
 
@@ -649,6 +657,53 @@ def bench_classes(blp, torch, lpgen, plan=None) -> dict:
     return res
 
 
+def lane_scaling(blp, torch, lpgen) -> dict:
+    """Tiny LPs (workload 1's recipe, 5 x 5) at several batch sizes: the
+    automatic choice (one LP per lane once the batch is large enough) against
+    one LP per wave forced (variant w1_r8_c8); device ms per step, median."""
+    names = [v[0] for v in blp.variants()]
+    w1 = names.index("w1_r8_c8")
+    res = {}
+    for K in (1_000, 16_384, 200_000):
+        db = blp.DeviceBatch.from_host(lpgen.config(1, range(K)))
+        e = {}
+        for mode, kw in (("automatic", {}), ("one_lp_per_wave", {"variant": w1})):
+            ts = []
+            _, _, out, bins = time_solver(blp, torch, db, 20, 5, profile=False, warm_ms=50.0, step_times=ts, **kw)
+            med = float(np.median(ts))
+            e[mode] = {"median_ms": round(med, 4), "lps_per_s": round(K / (med / 1e3), 1),
+                       "bins": {names[i]: int(bins[i]) for i in range(len(names)) if bins[i]}}
+        e["automatic_over_one_per_wave"] = round(e["one_lp_per_wave"]["median_ms"] / e["automatic"]["median_ms"], 3)
+        res[f"K{K}"] = e
+        log(f"lane scaling K={K}: {e}")
+    return res
+
+
+def graph_replay(blp, torch, lpgen, runs=50) -> dict:
+    """Captured launch sequence (hipGraph, replayed per batch signature)
+    against eager launches, on batches solved over and over: small batches,
+    where launch overheads weigh most.  Device time per step from HIP events
+    between back-to-back steps; results identical either way."""
+    res = {}
+    for name, hb in (("type1_5x5_x1000", lpgen.config(1, range(1000))),
+                     ("mixed_20..150_x2000", lpgen.config(5, range(2000), part="simplex")),
+                     ("mixed_5..300_x500", lpgen.config(4, range(500)))):
+        db = blp.DeviceBatch.from_host(hb)
+        e = {}
+        objs = {}
+        for mode, graph in (("eager", False), ("graph", True)):
+            ts = []
+            ms, _, out, _ = time_solver(blp, torch, db, runs, 5, profile=False, warm_ms=50.0, step_times=ts,
+                                        graph=graph)
+            e[mode] = {"median_ms": round(float(np.median(ts)), 4), "wall_ms_per_step": round(ms, 4)}
+            objs[mode] = out["obj"][:hb.count].cpu().numpy().view(np.int64)
+        e["graph_over_eager"] = round(e["graph"]["median_ms"] / e["eager"]["median_ms"], 3)
+        e["identical"] = bool(np.array_equal(objs["eager"], objs["graph"]))
+        res[name] = e
+        log(f"graph replay {name}: {e}")
+    return res
+
+
 def autotune_gain(blp, torch, db, K, base_ms, sample=256, runs=3) -> dict:
     """The autotuner on the batch itself (a calibration sample per size bin,
     every variant able to hold the bin), then the tuned solve timed."""
@@ -666,10 +721,12 @@ def autotune_gain(blp, torch, db, K, base_ms, sample=256, runs=3) -> dict:
     path = os.path.join(tempfile.mkdtemp(), "tune.json")
     s.autotune(db, sample=sample, cache_path=path)
     s.close()
+    deep = json.load(open(path)).get("streaming_deep")
     ts = []
     ms, _, out, _ = time_solver(blp, torch, db, runs, 0, profile=False, step_times=ts, tune_cache=path)
     med = float(np.median(ts))
     return {"sample_per_bin": sample, "tuning_s": round(tune_s, 2), "remap": changed,
+            "streaming_loads_in_flight": {1: 32, 0: 8}.get(deep, "automatic"),
             "device_ms": _stats(ts), "lps_per_s": round(K / (med / 1e3), 1),
             "gain_vs_untuned": round(base_ms / med, 3)}
 

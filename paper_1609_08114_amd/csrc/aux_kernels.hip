@@ -45,6 +45,7 @@ __device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, in
     // a variant for LPs without artificial rows under the largest-
     // coefficient rule takes only those
     const bool t1 = nart == 0 && vt.lpc;
+    const int64_t K = vt.count;
     if (vt.force >= 0) {
         if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols &&
             (t1 || !vt.type1[vt.force]))
@@ -52,7 +53,7 @@ __device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, in
     } else if (vt.force == -1) {
         long best = -1;
         for (int v = 0; v < vt.nreg; ++v) {
-            if (vt.rows[v] >= rows && vt.cols[v] >= cols && (t1 || !vt.type1[v])) {
+            if (vt.rows[v] >= rows && vt.cols[v] >= cols && (t1 || !vt.type1[v]) && K >= vt.min_count[v]) {
                 const long area = (long)vt.rows[v] * vt.cols[v];
                 if (best < 0 || area < best) {
                     best = area;

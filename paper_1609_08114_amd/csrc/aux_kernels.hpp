@@ -16,11 +16,13 @@ constexpr int kBoxTileMaxN = 48;
 // Register-tile variant shapes handed to the classify kernel.
 struct VariantTable {
     int nreg;
+    int64_t count;  // LPs of the batch
     int force;  // -1 automatic, -2 streaming only, >= 0 one variant
     int rows[kMaxVariants];
     int cols[kMaxVariants];
     int remap[kMaxVariants];  // autotuned replacement of each variant (nreg = streaming)
     int type1[kMaxVariants];  // 1: the variant takes only LPs without artificial rows under LPC
+    int64_t min_count[kMaxVariants];  // automatic choice: only for batches of at least this many LPs
     int lpc;                  // 1: the largest-coefficient rule (else the random rule)
 };
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -145,6 +146,7 @@ struct blp_handle_s {
 #endif
     // kernel-variant remap (autotuner); identity by default
     int remap[kMaxVariants] = {};
+    int tuned_deep = -1;  // streaming kernel's loads in flight: -1 automatic, 0 eight, 1 thirty-two
     // captured launch sequence of the last persistent solve
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_sig;
@@ -209,6 +211,15 @@ static bool can_replace(blp_handle h, int w, int v) {
     if (w >= h->nreg) return true;
     return h->variants[w].max_rows >= h->variants[v].max_rows && h->variants[w].max_cols >= h->variants[v].max_cols &&
            (!h->variants[w].type1_only || h->variants[v].type1_only);
+}
+
+// Smallest batch for which the automatic choice may use variant v: a variant
+// that packs several LPs into a workgroup (the lane kernel, 64 per wave)
+// needs a quarter of its workgroups per CU to beat one LP per wave; smaller
+// batches leave most of the GPU idle with it.
+static int64_t auto_min_count(blp_handle h, int v) {
+    const int64_t per = h->variants[v].lps_per_block;
+    return per > 1 ? per * h->cu_count / 4 : 0;
 }
 
 // Persistent grid of register variant v for `lps` LPs: its occupancy-sized
@@ -424,6 +435,7 @@ struct SolvePlan {
     bool gm_deep = false;  // some LP cannot be held by any register tile: the streaming bin is not empty
     size_t gm_lds = 0;
     std::vector<char> maybe;  // register variants that can receive LPs
+    bool may_stream = false;  // some simplex LP may reach the streaming kernel
     // device buffers of this solve (the handle's own, or carved from an arena)
     int32_t* counters = nullptr;
     int32_t* binid = nullptr;
@@ -463,7 +475,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     std::vector<VariantShape> shapes((size_t)h->nreg);
     bool remap_streams = false;
     for (int v = 0; v < h->nreg; ++v) {
-        shapes[v] = {h->variants[v].max_rows, h->variants[v].max_cols, h->variants[v].type1_only};
+        shapes[v] = {h->variants[v].max_rows, h->variants[v].max_cols, h->variants[v].type1_only,
+                     auto_min_count(h, v)};
         remap_streams |= h->remap[v] >= h->nreg;
     }
     PlanIn in;
@@ -493,8 +506,9 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     const bool any_simplex = pl.any_simplex, any_box = pl.any_box;
     const int64_t n_box = pl.n_box, tot_m = pl.tot_m, tot_n = pl.tot_n, max_slot = pl.max_slot;
     const int64_t n_may_stream = pl.n_may_stream;
+    sp.may_stream = n_may_stream > 0;
     const int max_m = pl.max_m, max_cols = pl.max_cols;
-    sp.gm_deep = pl.gm_deep;
+    sp.gm_deep = h->tuned_deep >= 0 ? h->tuned_deep != 0 : pl.gm_deep;
     sp.box_n = pl.box_n;
 
     // ---- outputs
@@ -611,7 +625,7 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
                 long barea = -1;
                 for (int v = 0; v < nreg; ++v)
                     if (h->variants[v].max_rows >= m + 2 && h->variants[v].max_cols >= n + nart + 1 &&
-                        (t1 || !h->variants[v].type1_only)) {
+                        (t1 || !h->variants[v].type1_only) && K >= auto_min_count(h, v)) {
                         long a = (long)h->variants[v].max_rows * h->variants[v].max_cols;
                         if (barea < 0 || a < barea) {
                             barea = a;
@@ -664,15 +678,17 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     return BLP_SUCCESS;
 }
 
-static VariantTable variant_table(blp_handle h) {
+static VariantTable variant_table(blp_handle h, int64_t count) {
     VariantTable vt{};
     vt.nreg = h->nreg;
+    vt.count = count;
     vt.force = h->opt.variant;
     for (int v = 0; v < h->nreg && v < kMaxVariants; ++v) {
         vt.rows[v] = h->variants[v].max_rows;
         vt.cols[v] = h->variants[v].max_cols;
         vt.remap[v] = h->remap[v];
         vt.type1[v] = h->variants[v].type1_only;
+        vt.min_count[v] = auto_min_count(h, v);
     }
     vt.lpc = h->opt.pivot_rule == BLP_RULE_LPC;
     return vt;
@@ -688,7 +704,7 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     // zero the counters and the striped bin counters (bin_off is rewritten)
     int32_t* stripes = bin_count + 4 * nbins;
     HIP_TRY(h, launch_reset(bin_count, (4 + kBinStripes) * nbins, s));
-    HIP_TRY(h, launch_classify(sp.P, variant_table(h), sp.binid, stripes, s));
+    HIP_TRY(h, launch_classify(sp.P, variant_table(h, sp.P.count), sp.binid, stripes, s));
     HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
     HIP_TRY(h, launch_scatter(sp.P.count, nbins, sp.binid, sp.P.bin_off, bin_fill, sp.list, s));
     // a uniform batch has one cost per bin; otherwise the kernels pop the
@@ -716,7 +732,9 @@ static blp_error enqueue_persistent(blp_handle h, SolvePlan& sp, hipStream_t s, 
     std::vector<int> cls;  // 0..nreg-1 register variants, nreg streaming
     for (int v = 0; v < nreg; ++v)
         if (sp.maybe[v]) cls.push_back(v);
-    if (sp.any_simplex) cls.push_back(nreg);
+    // the streaming launch is left out when every LP surely fits a register
+    // tile (an empty launch still costs a few microseconds on the stream)
+    if (sp.any_simplex && sp.may_stream) cls.push_back(nreg);
     const int nc = (int)cls.size();
     const bool forked = !capturing && nc > 1 && !sp.uni && K >= kForkMinLps;
     const int nf = forked ? std::min(nc - 1, (int)blp_handle_s::kForks) : 0;
@@ -1456,7 +1474,7 @@ static blp_error write_tuning(blp_handle h, const char* path) {
     for (int v = 0; v < h->nreg; ++v)
         std::fprintf(f, "%s\n    \"%s\": \"%s\"", v ? "," : "", h->variants[v].name,
                      h->remap[v] < h->nreg ? h->variants[h->remap[v]].name : "streaming");
-    std::fprintf(f, "\n  }\n}\n");
+    std::fprintf(f, "\n  },\n  \"streaming_deep\": %d\n}\n", h->tuned_deep);
     std::fclose(f);
     return BLP_SUCCESS;
 }
@@ -1501,6 +1519,14 @@ blp_error blp_load_tuning(blp_handle h, const char* path) {
         remap[v] = w;
     }
     for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = remap[v];
+    // the streaming kernel's depth (absent in older tables: automatic)
+    h->tuned_deep = -1;
+    const size_t dp = txt.find("\"streaming_deep\": ");
+    if (dp != std::string::npos) {
+        const int d = std::atoi(txt.c_str() + dp + std::strlen("\"streaming_deep\": "));
+        if (d < -1 || d > 1) return fail(h, BLP_ERR_ARG, "malformed streaming_deep in %s", path);
+        h->tuned_deep = d;
+    }
     if (h->graph_exec) {
         (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
@@ -1530,12 +1556,14 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         saved[v] = h->remap[v];
         h->remap[v] = v;
     }
-    const int saved_force = h->opt.variant;
+    const int saved_force = h->opt.variant, saved_deep = h->tuned_deep;
     h->opt.variant = -1;
+    h->tuned_deep = -1;
     SolvePlan sp;
     blp_error e = prepare(h, B, nullptr, s, sp, /*stream_all=*/true);
     if (e == BLP_SUCCESS) e = enqueue_binning(h, sp, s);
     h->opt.variant = saved_force;
+    h->tuned_deep = saved_deep;
     if (e != BLP_SUCCESS || sp.box_only_uniform) {
         for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = saved[v];
         return e;
@@ -1588,9 +1616,51 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         }
         saved[v] = best;
     }
+    // the streaming kernel's loads in flight per lane (8 or 32), timed on a
+    // sample of the streaming bin, each depth with its own occupancy-sized
+    // grid (never more workgroups than the workspace has slots)
+    int deep = saved_deep;
+    if (cnt[nreg] > 0) {
+        const int S = std::min<int>(sample, cnt[nreg]);
+        HIP_TRY(h, h->tune.reserve(sizeof(int32_t) * (4 + (size_t)S)));
+        int32_t* tb = h->tune.as<int32_t>();
+        int32_t hdr[3] = {0, S, 0};
+        HIP_TRY(h, hipMemcpyAsync(tb, hdr, sizeof hdr, hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(tb + 4, sp.list + off[nreg], sizeof(int32_t) * S, hipMemcpyDeviceToDevice, s));
+        KParams Q = sp.P;
+        Q.list = tb + 4;
+        Q.bin_off = tb;
+        Q.bin_len = tb + 1;
+        Q.bin_head = tb + 2;
+        Q.bin = 0;
+        Q.direct = 0;
+        float best_ms = -1.f;
+        for (int d = 0; d < 2; ++d) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld, d != 0), gm_threads(),
+                                                             sp.gm_lds) != hipSuccess ||
+                occ < 1)
+                occ = 1;
+            const int grid = (int)std::min<int64_t>(std::min<int64_t>((int64_t)occ * h->cu_count, sp.gm_workers), S);
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+                HIP_TRY(h, launch_reset(tb + 2, 1, s));
+                HIP_TRY(h, hipEventRecord(e0, s));
+                HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s, d != 0));
+                HIP_TRY(h, hipEventRecord(e1, s));
+                HIP_TRY(h, hipEventSynchronize(e1));
+                HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+            }
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                deep = d;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = saved[v];
+    h->tuned_deep = deep;
     if (h->graph_exec) {
         (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;

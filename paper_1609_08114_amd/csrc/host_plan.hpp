@@ -23,6 +23,7 @@ enum { PLAN_OK = 0, PLAN_ERR_ARG = 1, PLAN_ERR_NOMEM = 2, PLAN_ERR_TOO_LARGE = 5
 struct VariantShape {
     int rows, cols;  // largest tableau (rows incl. objective rows, columns incl. rhs)
     int type1 = 0;   // 1: takes only LPs without artificial rows under the largest-coefficient rule
+    int64_t min_count = 0;  // the automatic choice takes it only for batches of at least this many LPs
 };
 
 struct PlanIn {
@@ -96,7 +97,9 @@ inline int plan_batch(const PlanIn& in, Plan& p) {
         if (in.stream_all || in.force == -2 || in.remap_streams) return false;
         for (int v = 0; v < in.nreg; ++v) {
             if (in.force >= 0 && v != in.force) continue;
-            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + m + 1 && !in.variants[v].type1) return true;
+            if (in.variants[v].rows >= m + 2 && in.variants[v].cols >= n + m + 1 && !in.variants[v].type1 &&
+                (in.force >= 0 || in.count >= in.variants[v].min_count))
+                return true;
         }
         return false;
     };

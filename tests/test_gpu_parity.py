@@ -227,16 +227,26 @@ def test_lane_kernel_tiny_lps():
             c = rng.integers(-2, 6, size=n).astype(float)
             sense = rng.integers(0, 2, size=m).astype(np.int8)
         lps.append(dict(A=A, b=b, c=c, sense=sense))
-    hb = crafted_batch(lps)
+    # six copies: the automatic choice takes the lane kernel only for
+    # batches that give it a quarter of a workgroup per CU (16,384 LPs)
+    hb = crafted_batch(lps * 6)
     g, o = _both(hb, tag="lane-tiny")
     names = [v[0] for v in blp.variants()]
     lane = [i for i, nm in enumerate(names) if nm.startswith("l64_")]
     assert len(lane) == 2 and all(g["bins"][i] > 64 for i in lane), g["bins"]
     assert set(np.unique(o["status"])) >= {0, 1, 2}
+    # a small batch leaves it to one LP per wave, with the same bits
+    small = crafted_batch(lps)
+    gs = gpu_solve(small)
+    assert all(gs["bins"][i] == 0 for i in lane), gs["bins"]
+    K = len(lps)
+    for k in ("status", "iters"):
+        assert np.array_equal(gs[k], g[k][:K]), k
+    assert np.array_equal(gs["obj"].view(np.int64), g["obj"][:K].view(np.int64))
     sub = crafted_batch(lps[:700])
-    a = gpu_solve(sub)
+    a = gpu_solve(sub, variant=lane[0])
     for mode in (1, 2):
-        b = gpu_solve(sub, mode=mode)
+        b = gpu_solve(sub, mode=mode, variant=lane[0])
         for k in ("status", "iters"):
             assert np.array_equal(a[k], b[k]), (mode, k)
         for k in ("obj", "x", "y"):
