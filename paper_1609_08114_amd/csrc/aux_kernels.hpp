@@ -66,6 +66,10 @@ void shared_shape(int* rows, int* cols);
 // lane for tableaux of 129..256 rows as well).
 hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s, bool deep = false);
 const void* gm_kernel_ptr(int ld, bool deep = false);
+// allow `bytes` of dynamic LDS for both layouts' instantiations of a geometry
+hipError_t gm_allow_lds(int ld, bool deep, int bytes);
+// whether a deep instantiation exists for tableaux of `ld` rows
+bool gm_has_deep(int ld);
 int gm_threads();
 size_t gm_lds_bytes_host(int ld, int cols);
 

@@ -60,6 +60,7 @@ struct KParams {
     int64_t ws_slot;
     int32_t ws_ld;   // leading dimension (rows, multiple of 16)
     int32_t ws_cols; // columns available per slot
+    int32_t ws_lds;  // doubles of dynamic LDS for on-chip columns (0: none)
     // phase cycle counters (only with -DBLP_PHASE_TIMERS; NULL otherwise)
     unsigned long long* timers;
     // entering rule: 0 largest coefficient, 1 random positive coefficient

@@ -111,6 +111,7 @@ struct blp_handle_s {
     blp_options opt;
     std::string err;
     int cu_count = 0;
+    size_t lds_per_cu = 0, lds_per_block = 0;  // bytes
     const RegVariant* variants = nullptr;
     int nreg = 0;
     void* scratch = nullptr;  // this device's copy of the static scratch (allocation-free entry point)
@@ -323,6 +324,8 @@ blp_error blp_create(blp_handle* out, const blp_options* opt) {
         return BLP_ERR_HIP;
     }
     h->cu_count = prop.multiProcessorCount;
+    h->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+    h->lds_per_block = std::max(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
     h->variants = reg_variants(&h->nreg);
     for (int v = 0; v < kMaxVariants; ++v) h->remap[v] = v;
     if (o.variant >= h->nreg || h->nreg > kMaxVariants) {
@@ -426,13 +429,47 @@ void blp_destroy(blp_handle h) {
 
 const char* blp_last_error(blp_handle h) { return h ? h->err.c_str() : "null handle"; }
 
+// Dynamic LDS of a streaming launch: the mirrors, and for the deep
+// instantiation (a bin known to hold LPs) on-chip tableau columns in what the
+// CU's LDS has left at the kernel's register-limited occupancy, less 16 KiB
+// when workgroups of register kernels may share the CU (`shared`).  Sets
+// *bytes, *tab (doubles of on-chip columns) and *occ (workgroups per CU, at
+// least 1).
+static void gm_lds_plan(blp_handle h, int ld, int cols, bool deep, bool shared, size_t* bytes, int32_t* tab,
+                        int* occ) {
+    const void* fn = gm_kernel_ptr(ld, deep);
+    const size_t mirrors = gm_lds_bytes_host(ld, cols);
+    *bytes = mirrors;
+    *tab = 0;
+    *occ = 1;
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fn, gm_threads(), mirrors) != hipSuccess || o < 1) return;
+    *occ = o;
+    hipFuncAttributes fa{};
+    if (!deep || !gm_has_deep(ld) || hipFuncGetAttributes(&fa, fn) != hipSuccess) return;
+    const size_t kReserve = shared ? (16u << 10) : 0;
+    const size_t per = std::min(h->lds_per_cu / (size_t)o, h->lds_per_block);
+    if (per <= mirrors + fa.sharedSizeBytes + kReserve + 1024) return;
+    const size_t t = (per - mirrors - fa.sharedSizeBytes - kReserve) / sizeof(double);
+    const size_t want = mirrors + sizeof(double) * t;
+    int o2 = 0;
+    if (gm_allow_lds(ld, deep, (int)want) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, fn, gm_threads(), want) != hipSuccess || o2 < o) {
+        (void)hipGetLastError();
+        return;
+    }
+    *bytes = want;
+    *tab = (int32_t)t;
+}
+
 // Everything one solve needs after validation.
 struct SolvePlan {
     KParams P{};
     bool uni = false, any_simplex = false, any_box = false, box_only_uniform = false;
     int64_t n_box = 0;
     int gm_ld = 0, gm_cols = 0, gm_workers = 0;
-    bool gm_deep = false;  // some LP cannot be held by any register tile: the streaming bin is not empty
+    bool gm_deep = false;  // the streaming kernel's deep instantiation (deep loads, on-chip columns)
+    bool gm_shared = false;  // register kernels may run beside it (keep LDS for them)
     size_t gm_lds = 0;
     std::vector<char> maybe;  // register variants that can receive LPs
     bool may_stream = false;  // some simplex LP may reach the streaming kernel
@@ -508,6 +545,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     const int64_t n_may_stream = pl.n_may_stream;
     sp.may_stream = n_may_stream > 0;
     const int max_m = pl.max_m, max_cols = pl.max_cols;
+    // deep when some LP cannot be held by any register tile (the streaming
+    // bin is not empty), unless the autotuner chose
     sp.gm_deep = h->tuned_deep >= 0 ? h->tuned_deep != 0 : pl.gm_deep;
     sp.box_n = pl.box_n;
 
@@ -646,12 +685,9 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     if (any_simplex) {
         sp.gm_ld = ((max_m + 2 + 15) / 16) * 16;  // 128-byte aligned columns
         sp.gm_cols = max_cols;
-        sp.gm_lds = gm_lds_bytes_host(sp.gm_ld, sp.gm_cols);
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld, sp.gm_deep), gm_threads(), sp.gm_lds) !=
-                hipSuccess ||
-            occ < 1)
-            occ = 1;
+        int occ = 1;
+        sp.gm_shared = std::find(sp.maybe.begin(), sp.maybe.end(), (char)1) != sp.maybe.end();
+        gm_lds_plan(h, sp.gm_ld, sp.gm_cols, sp.gm_deep, sp.gm_shared, &sp.gm_lds, &P.ws_lds, &occ);
         if (h->opt.workers_per_cu > 0) occ = std::min(occ, (int)h->opt.workers_per_cu);
         // one workspace slot per streaming workgroup, no more workgroups
         // than LPs that can reach the streaming kernel
@@ -1636,17 +1672,15 @@ blp_error blp_autotune(blp_handle h, const blp_batch* B, int32_t sample, const c
         Q.direct = 0;
         float best_ms = -1.f;
         for (int d = 0; d < 2; ++d) {
-            int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gm_kernel_ptr(sp.gm_ld, d != 0), gm_threads(),
-                                                             sp.gm_lds) != hipSuccess ||
-                occ < 1)
-                occ = 1;
+            int occ = 1;
+            size_t lds = 0;
+            gm_lds_plan(h, sp.gm_ld, sp.gm_cols, d != 0, sp.gm_shared, &lds, &Q.ws_lds, &occ);
             const int grid = (int)std::min<int64_t>(std::min<int64_t>((int64_t)occ * h->cu_count, sp.gm_workers), S);
             float ms = 0.f;
             for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
                 HIP_TRY(h, launch_reset(tb + 2, 1, s));
                 HIP_TRY(h, hipEventRecord(e0, s));
-                HIP_TRY(h, launch_gm(Q, grid, sp.gm_lds, s, d != 0));
+                HIP_TRY(h, launch_gm(Q, grid, lds, s, d != 0));
                 HIP_TRY(h, hipEventRecord(e1, s));
                 HIP_TRY(h, hipEventSynchronize(e1));
                 HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));

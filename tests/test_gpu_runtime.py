@@ -7,7 +7,7 @@ import pytest
 
 import lpgen
 import oracle
-from solve_util import compare, compare_scattered, gpu_solve, scattered_batch
+from solve_util import compare, compare_scattered, crafted_batch, gpu_solve, scattered_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +86,41 @@ def test_autotune_remap_and_cache(tmp_path):
     blp.blp_load_tuning(s2.h, path)
     assert np.array_equal(blp.blp_tuning(s2.h), remap)
     s2.close()
+
+
+@pytest.mark.parametrize("deep", [0, 1])
+def test_streaming_kernel_every_size(tmp_path, deep):
+    """Every LP through the streaming kernel (a tuning file that remaps each
+    register variant to it), with shallow loads and HBM columns only (deep 0)
+    or deep loads and on-chip columns (deep 1): LPs of 5..300 rows and
+    columns, so that tableaux of every height class run, some wholly on chip
+    and some split between LDS and HBM, plus the crafted statuses; strict
+    against the oracle."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    from test_gpu_parity import _crafted_lps
+    w4 = lpgen.config(4, range(1200, 1280))
+    lps = []
+    for k in range(w4.count):
+        m, n, co = int(w4.m[k]), int(w4.n[k]), int(w4.col_off[k])
+        if w4.kind[k] == 1:
+            lps.append(dict(c=w4.c[co:co + n], l=w4.l[co:co + n], u=w4.u[co:co + n]))
+        else:
+            ao, ro = int(w4.a_off[k]), int(w4.row_off[k])
+            lps.append(dict(A=w4.A[ao:ao + m * n].reshape(m, n), b=w4.b[ro:ro + m], c=w4.c[co:co + n],
+                            sense=w4.sense[ro:ro + m]))
+    hb = crafted_batch(lps + _crafted_lps())
+    props = torch.cuda.get_device_properties(0)
+    names = [v[0] for v in blp.variants()]
+    path = str(tmp_path / "all_streaming.json")
+    with open(path, "w") as f:
+        json.dump({"arch": props.gcnArchName, "cus": props.multi_processor_count,
+                   "remap": {v: "streaming" for v in names}, "streaming_deep": deep}, f, indent=2)
+    g = gpu_solve(hb, tune_cache=path)
+    bins = g["bins"]
+    assert bins[len(names)] == int((hb.kind == 0).sum()), bins
+    compare(hb, g, oracle.solve_batch(hb), strict=True, tag=f"streaming-deep{deep}")
 
 
 def test_profile_and_bins():
