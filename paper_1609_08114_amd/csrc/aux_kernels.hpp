@@ -62,8 +62,9 @@ int shared_threads();
 void shared_shape(int* rows, int* cols);
 
 // Streaming kernel (simplex_gm.hip).
-// deep: the launch's bin is known not to be empty (32 loads in flight per
-// lane for tableaux of 129..256 rows as well).
+// deep: the launch's bin is known not to be empty: for tableaux of up to 512
+// rows, more loads in flight per lane and on-chip columns in the dynamic LDS
+// beyond the mirrors (P.ws_lds doubles; lds_bytes must cover both).
 hipError_t launch_gm(const KParams& P, int grid, size_t lds_bytes, hipStream_t s, bool deep = false);
 const void* gm_kernel_ptr(int ld, bool deep = false);
 // allow `bytes` of dynamic LDS for both layouts' instantiations of a geometry
