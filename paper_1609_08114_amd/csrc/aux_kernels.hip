@@ -311,14 +311,25 @@ __global__ void __launch_bounds__(256) backward_hyperbox_flat_kernel(KParams P, 
                                                                       double* dl, double* du) {
     const int N = P.un;
     const int64_t E = P.count * (int64_t)N;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = e / N;
+    // LP k = e / N advances with e (one division per thread, not per element)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x, e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t dk = stride / N;
+    const int dr = (int)(stride - dk * N);
+    int64_t k = e0 / N;
+    int r = (int)(e0 - k * N);
+    for (int64_t e = e0; e < E; e += stride) {
         const bool ok = P.status[k] == ST_OPTIMAL;
         const double gk = ok ? g[k] : 0.0;
         const double ci = P.c[e];
         if (dc) dc[e] = ok ? gk * P.x[e] : 0.0;
         if (dl) dl[e] = ok && ci < 0.0 ? gk * ci : 0.0;
         if (du) du[e] = ok && !(ci < 0.0) ? gk * ci : 0.0;
+        k += dk;
+        r += dr;
+        if (r >= N) {
+            r -= N;
+            ++k;
+        }
     }
 }
 
@@ -389,11 +400,20 @@ __global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const 
             for (int j = threadIdx.x; j < L.n; j += blockDim.x) dc[L.col_off + j] = ok ? gk * x[j] : 0.0;
         if (db)
             for (int i = threadIdx.x; i < L.m; i += blockDim.x) db[L.row_off + i] = ok ? gk * y[i] : 0.0;
-        if (dA) {
-            const int64_t mn = (int64_t)L.m * L.n;
-            for (int64_t e = threadIdx.x; e < mn; e += blockDim.x) {
-                const int i = (int)(e / L.n), j = (int)(e - (int64_t)i * L.n);
+        if (dA && L.n > 0) {
+            // element e = i n + j; (i, j) advance with e instead of a
+            // division per element (m n < 2^31 by the size limits)
+            const int n = L.n, mn = L.m * n, step = (int)blockDim.x;
+            const int di = step / n, dj = step - di * n;
+            int i = (int)threadIdx.x / n, j = (int)threadIdx.x - i * n;
+            for (int e = threadIdx.x; e < mn; e += step) {
                 dA[L.a_off + e] = ok ? -(gk * y[i]) * x[j] : 0.0;
+                i += di;
+                j += dj;
+                if (j >= n) {
+                    j -= n;
+                    ++i;
+                }
             }
         }
     }

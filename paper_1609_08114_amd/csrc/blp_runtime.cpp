@@ -117,6 +117,7 @@ struct blp_handle_s {
     void* scratch = nullptr;  // this device's copy of the static scratch (allocation-free entry point)
     std::vector<int> reg_workers;  // persistent grid per variant
     int gm_occ = 1;
+    int direct_v = -1;  // the last solve's one-launch variant (no binning), or -1
     // device buffers
     DevBuf meta;     // m, n, kind (int32) + a_off, row_off, col_off (int64) for non-uniform batches
     DevBuf counters; // bin_count, bin_fill, bin_head, bin_off (4 x nbins int32), striped bin counters
@@ -472,6 +473,7 @@ struct SolvePlan {
     bool gm_shared = false;  // register kernels may run beside it (keep LDS for them)
     size_t gm_lds = 0;
     std::vector<char> maybe;  // register variants that can receive LPs
+    int direct_v = -1;        // >= 0: one launch of this variant, LP k in workgroup k, no binning
     bool may_stream = false;  // some simplex LP may reach the streaming kernel
     // device buffers of this solve (the handle's own, or carved from an arena)
     int32_t* counters = nullptr;
@@ -509,6 +511,8 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
                          bool stream_all = false, Arena* arena = nullptr, size_t ws_budget = 0) {
     const int64_t K = B->count;
     const bool uni = B->uniform != 0;
+    // per-class kernel times report this solve's classes only
+    std::fill(h->ev_used.begin(), h->ev_used.end(), (char)0);
     std::vector<VariantShape> shapes((size_t)h->nreg);
     bool remap_streams = false;
     for (int v = 0; v < h->nreg; ++v) {
@@ -679,6 +683,27 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             }
         } else {
             std::fill(sp.maybe.begin(), sp.maybe.end(), 1);
+        }
+    }
+    // A uniform batch small enough that every LP gets a workgroup of its own
+    // at once, with a register variant that holds the shape whatever its
+    // number of artificial rows: one launch, LP k in workgroup k.  Binning
+    // would only choose among tiles that give the same bits, and it costs
+    // four launches, about as long as solving such a batch.
+    sp.direct_v = -1;
+    if (uni && any_simplex && h->opt.variant == -1 && h->opt.mode == BLP_MODE_PERSISTENT) {
+        const int m = h->plan.m[0], n = h->plan.n[0];
+        long barea = -1;
+        for (int v = 0; v < nreg; ++v) {
+            const RegVariant& rv = h->variants[v];
+            if (rv.max_rows >= m + 2 && rv.max_cols >= n + m + 1 && !rv.type1_only && rv.lps_per_block == 1 &&
+                h->remap[v] == v && K <= h->reg_workers[v]) {
+                const long a = (long)rv.max_rows * rv.max_cols;
+                if (barea < 0 || a < barea) {
+                    barea = a;
+                    sp.direct_v = v;
+                }
+            }
         }
     }
     // Streaming-kernel geometry: worst case over the batch's simplex LPs.
@@ -881,6 +906,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
                                (uint64_t)P.ws_cols, (uint64_t)(uintptr_t)P.m, (uint64_t)(uintptr_t)sp.binid,
                                (uint64_t)sp.gm_lds, (uint64_t)sp.gm_workers, (uint64_t)sp.gm_deep};
     for (int v = 0; v < h->nreg; ++v) g.push_back((uint64_t)sp.maybe[v] | ((uint64_t)h->remap[v] << 8));
+    g.push_back((uint64_t)(int64_t)sp.direct_v);
     g.push_back((uint64_t)P.pivot_rule);
     g.push_back((uint64_t)P.layout);
     g.push_back(P.seed);
@@ -901,6 +927,7 @@ static std::vector<uint64_t> graph_signature(blp_handle h, const SolvePlan& sp, 
 static void record_solve(blp_handle h, const SolvePlan& sp, int64_t K) {
     h->last = sp.P;
     h->last.direct = 0;
+    h->direct_v = sp.direct_v;
     h->count = K;
     h->uniform = sp.uni;
     h->any_simplex = sp.any_simplex;
@@ -912,7 +939,22 @@ static void record_solve(blp_handle h, const SolvePlan& sp, int64_t K) {
     h->solved = true;
 }
 
+static blp_error enqueue_direct(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    const int v = sp.direct_v;
+    KParams Q = sp.P;
+    Q.list = nullptr;  // the identity list
+    Q.direct = 1;
+    Q.direct_first = 0;
+    Q.direct_end = 0;
+    Q.bin = v;
+    HIP_TRY(h, h->mark(v, true, s));
+    HIP_TRY(h, h->variants[v].launch(Q, (int)Q.count, s));
+    HIP_TRY(h, h->mark(v, false, s));
+    return BLP_SUCCESS;
+}
+
 static blp_error enqueue_eager(blp_handle h, SolvePlan& sp, hipStream_t s) {
+    if (sp.direct_v >= 0 && h->opt.mode == BLP_MODE_PERSISTENT) return enqueue_direct(h, sp, s);
     blp_error e = enqueue_binning(h, sp, s);
     if (e != BLP_SUCCESS) return e;
     e = h->opt.mode == BLP_MODE_PERSISTENT ? enqueue_persistent(h, sp, s) : enqueue_baseline(h, sp, s);
@@ -1079,9 +1121,14 @@ blp_error blp_solve_batch(blp_handle h, const blp_batch* B, const blp_outputs* o
             hipStream_t cs = h->cap_stream;
             hipGraph_t g = nullptr;
             HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            blp_error ce = enqueue_binning(h, sp, cs);
-            if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, cs, true);
-            if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, cs);
+            blp_error ce = BLP_SUCCESS;
+            if (sp.direct_v >= 0) {
+                ce = enqueue_direct(h, sp, cs);
+            } else {
+                ce = enqueue_binning(h, sp, cs);
+                if (ce == BLP_SUCCESS) ce = enqueue_persistent(h, sp, cs, true);
+                if (ce == BLP_SUCCESS) ce = enqueue_hyperbox(h, sp, cs);
+            }
             hipError_t he = hipStreamEndCapture(cs, &g);
             if (ce != BLP_SUCCESS) {
                 if (g) (void)hipGraphDestroy(g);
@@ -1733,7 +1780,9 @@ blp_error blp_last_bins(blp_handle h, int64_t* counts, int32_t* n_classes) {
     HIP_TRY(h, hipSetDevice(h->opt.device));
     HIP_TRY(h, wait_last(h));
     std::vector<int32_t> c(nbins, 0);
-    if (h->last.list) {
+    if (h->direct_v >= 0) {
+        c[h->direct_v] = (int32_t)h->count;
+    } else if (h->last.list) {
         HIP_TRY(h, hipMemcpy(c.data(), h->last.bin_len, sizeof(int32_t) * nbins, hipMemcpyDeviceToHost));
     } else {
         c[h->nreg + 1] = (int32_t)h->count;

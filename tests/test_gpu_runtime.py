@@ -123,6 +123,41 @@ def test_streaming_kernel_every_size(tmp_path, deep):
     compare(hb, g, oracle.solve_batch(hb), strict=True, tag=f"streaming-deep{deep}")
 
 
+def test_small_uniform_batch_runs_as_one_launch():
+    """A uniform batch whose LPs all get a workgroup at once runs as one
+    launch (LP k in workgroup k) of a variant that holds its shape for any
+    number of artificial rows, with no binning launches: strict against the
+    oracle, and the same bits in graph mode; a uniform batch too large for
+    that is still binned."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    hb = lpgen.config(1, range(1000))
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver(profile=True)
+    out = s.solve(db)
+    torch.cuda.synchronize()
+    bins = blp.blp_last_bins(s.h)
+    ms = blp.blp_last_kernel_ms(s.h)
+    s.close()
+    nz = np.nonzero(bins)[0]
+    assert len(nz) == 1 and bins[nz[0]] == 1000, bins
+    _, rows, cols = blp.variants()[nz[0]]
+    assert rows >= 5 + 2 and cols >= 5 + 5 + 1
+    assert ms[nz[0]] > 0 and ms[-1] == 0, ms  # no binning
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("status", "iters", "obj"):
+        g[k] = g[k][:1000]
+    compare(hb, g, oracle.solve_batch(hb), strict=True, tag="one-launch")
+    gg = gpu_solve(hb, graph=True)
+    for k in ("obj", "x", "y"):
+        assert np.array_equal(_bits(gg[k]), _bits(g[k])), k
+    big = lpgen.config(1, range(200_000))
+    gb = gpu_solve(big)
+    assert gb["bins"].sum() == 200_000 and gb["bins"][nz[0]] < 200_000, gb["bins"]
+    assert np.array_equal(_bits(gb["obj"][:1000]), _bits(g["obj"]))
+
+
 def test_profile_and_bins():
     import torch
 
