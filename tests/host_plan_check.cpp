@@ -6,8 +6,10 @@
 // check states a property of the result, not the planner's formulas.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <random>
 #include <set>
+#include <thread>
 
 #include "host_plan.hpp"
 
@@ -28,7 +30,99 @@ static int failures = 0;
 static const VariantShape kShapes[] = {{8, 8}, {7, 11}, {8, 8}, {16, 16}, {32, 32}, {64, 64}, {112, 112, 1},
                                        {112, 112}, {128, 112}, {128, 128}, {160, 160}};
 
-int main() {
+// Threads mode (built with ThreadSanitizer by the test): one planner per
+// thread, as with one handle per thread.  Random batches are planned once on
+// the main thread; then four threads plan all of them at once, each with its
+// own reused Plan and in its own order, and every result must equal the
+// serial one (the planner keeps no state outside its arguments).
+struct Case {
+    std::vector<int32_t> m, n, kind;
+    std::vector<int64_t> ao, ro, co;
+    PlanIn in;
+};
+static std::string digest(int rc, const Plan& p, bool uni) {
+    if (rc != PLAN_OK) return std::to_string(rc) + "|" + p.msg;  // a refused batch: the code and message only
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%d|%d|%d|%lld|%lld|%lld|%lld|%d|%d|%lld|%lld|%d|%d|", rc, (int)p.any_simplex,
+                  (int)p.any_box, (long long)p.n_box, (long long)p.tot_a, (long long)p.tot_m, (long long)p.tot_n,
+                  p.max_m, p.max_cols, (long long)p.max_slot, (long long)p.n_may_stream, (int)p.gm_deep, p.box_n);
+    std::string d = buf + p.msg + "|";
+    if (uni) return d;  // a uniform batch's offsets are implied (the vectors are not used)
+    for (size_t k = 0; k < p.a_off.size(); ++k)
+        d += std::to_string(p.a_off[k]) + "," + std::to_string(p.row_off[k]) + "," + std::to_string(p.col_off[k]) + ";";
+    return d;
+}
+static int threads_main() {
+    std::mt19937_64 rng(7);
+    auto U = [&](int lo, int hi) { return (int)std::uniform_int_distribution<int>(lo, hi)(rng); };
+    const int kNreg = (int)(sizeof kShapes / sizeof kShapes[0]);
+    std::vector<Case> cases(400);
+    for (Case& c : cases) {
+        const int64_t K = U(0, 50);
+        const bool uni = U(0, 3) == 0;
+        c.m.resize(K), c.n.resize(K), c.kind.resize(K), c.ao.resize(K), c.ro.resize(K), c.co.resize(K);
+        int64_t a = 0, r = 0, cc = 0;
+        for (int64_t k = 0; k < K; ++k) {
+            c.kind[k] = U(0, 4) == 0 ? 1 : 0;
+            c.n[k] = uni && k ? c.n[0] : U(1, 300);
+            c.m[k] = c.kind[k] ? 0 : (uni && k ? c.m[0] : U(1, 300));
+            if (uni && k) c.kind[k] = c.kind[0], c.m[k] = c.m[0];
+            if (U(0, 20) == 0) c.m[k] = 5000;  // an invalid entry now and then
+            a += U(0, 3), r += U(0, 3), cc += U(0, 3);
+            c.ao[k] = a, c.ro[k] = r, c.co[k] = cc;
+            a += (int64_t)c.m[k] * c.n[k], r += c.m[k], cc += c.n[k];
+        }
+        c.in.count = K;
+        c.in.uniform = uni;
+        c.in.has_A = c.in.has_b = c.in.has_sense = c.in.has_c = c.in.has_l = c.in.has_u = true;
+        c.in.variants = kShapes;
+        c.in.nreg = kNreg;
+        c.in.force = U(0, 5) == 0 ? U(-2, kNreg - 1) : -1;
+        c.in.lpc = U(0, 3) != 0;
+    }
+    for (Case& c : cases) {  // pointers once the vectors are final
+        c.in.m = c.m.data(), c.in.n = c.n.data(), c.in.kind = c.kind.data();
+        if (!c.in.uniform && c.m.size() % 2) c.in.a_off = c.ao.data(), c.in.row_off = c.ro.data(), c.in.col_off = c.co.data();
+    }
+    std::vector<std::string> want(cases.size());
+    {
+        Plan p;
+        for (size_t i = 0; i < cases.size(); ++i) want[i] = digest(plan_batch(cases[i].in, p), p, cases[i].in.uniform);
+    }
+    constexpr int kThreads = 4;
+    std::vector<int> bad(kThreads, 0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < kThreads; ++t)
+        th.emplace_back([&, t] {
+            Plan p;
+            std::vector<int64_t> order;
+            std::vector<CopyRun> runs;
+            for (int rep = 0; rep < 3; ++rep)
+                for (size_t q = 0; q < cases.size(); ++q) {
+                    const size_t i = (q * (2 * t + 1) + (size_t)rep * 97) % cases.size();
+                    if (digest(plan_batch(cases[i].in, p), p, cases[i].in.uniform) != want[i]) ++bad[t];
+                    if (!cases[i].in.uniform && p.code == PLAN_OK && !p.a_off.empty()) {
+                        std::vector<int32_t> len(cases[i].n.begin(), cases[i].n.end());
+                        int64_t lo = INT64_MAX;
+                        for (int64_t o : p.col_off) lo = std::min(lo, o);
+                        copy_runs(p.col_off, len, 0, (int64_t)len.size(), lo, order, runs);
+                        int64_t tot = 0;
+                        for (const CopyRun& r : runs) tot += r.len;
+                        int64_t sum = 0;
+                        for (int32_t l : len) sum += l;
+                        if (tot != sum) ++bad[t];
+                    }
+                }
+        });
+    for (std::thread& x : th) x.join();
+    int total = 0;
+    for (int b : bad) total += b;
+    std::printf("host plan threads: %d failures\n", total);
+    return total ? 1 : 0;
+}
+
+int main(int argc, char** argv) {
+    if (argc > 1 && std::strcmp(argv[1], "threads") == 0) return threads_main();
     std::mt19937_64 rng(20260111);
     auto U = [&](int lo, int hi) { return (int)std::uniform_int_distribution<int>(lo, hi)(rng); };
     Plan p;  // reused across calls, like the handle's
