@@ -246,6 +246,10 @@ def main():
     if timers:
         roofline["phase_cycles"] = timers
         log(f"phase timers: {timers}")
+    # the same batch with its recorded pivots replayed (no Steps 1 and 2)
+    if names[dom] == "b4_r112_c112":
+        roofline["pivot_replay"] = pivot_replay(blp, torch, db, K, obj, dom_ms, (m + 1) * (n + 1))
+        log(f"pivot replay: {roofline['pivot_replay']}")
 
     # ------------------------------------------------- one LP per launch
     S = min(args.one_per_launch_sample, K)
@@ -308,7 +312,7 @@ def main():
         cpu = {"value": round(C * reps / dt, 1), "unit": "LPs/s", "cores": cores, "kind": "oracle",
                "sample": f"first {C} LPs of the 50,000-LP batch (type 1, m=n=100) solved {reps} times, "
                          "OpenMP one LP per thread",
-               "seconds": round(dt, 3)}
+               "seconds": round(dt, 3), "single_core": oracle_single_core(1000), "host": host_cpu()}
         rel = np.abs(obj[:C] - ref["obj"]) / np.maximum(1.0, np.abs(ref["obj"]))
         parity = {"checked": C, "status_mismatch": int((status[:C] != ref["status"]).sum()),
                   "max_obj_relerr": float(rel.max()),
@@ -346,6 +350,75 @@ def main():
         "lane_kernel_scaling": lanes,
     }
     print(json.dumps(line), flush=True)
+
+
+def pivot_replay(blp, torch, db, K, obj, fused_ms, entries, runs=5) -> dict:
+    """Cross-check of the update time from the phase counters: the batch is
+    solved once recording every LP's pivots (leaving row, entering slot), then
+    `runs` times replaying them, so Steps 1 and 2 (pricing and the ratio test)
+    are skipped while the load, the column and row exchanges, the division,
+    the rank-1 updates and the extraction run as in the fused kernel."""
+    stride = 1 + 2 * 128
+    tr = torch.empty(K * stride, dtype=torch.int32, device="cuda")
+    s = blp.Solver(profile=True)
+    stream = torch.cuda.Stream()
+    v = [x[0] for x in blp.variants()].index("b4_r112_c112")
+    rec = s.pivot_trace(db, tr, stride, False, stream=stream)
+    torch.cuda.synchronize()
+    rec_ms = float(blp.blp_last_kernel_ms(s.h)[v])
+    cnt = tr.view(K, stride)[:, 0].cpu().numpy()
+    out = None
+    ts = []
+    for _ in range(runs):
+        out = s.pivot_trace(db, tr, stride, True, stream=stream, outputs=out)
+        torch.cuda.synchronize()
+        ts.append(float(blp.blp_last_kernel_ms(s.h)[v]))
+    st = out["status"][:K].cpu().numpy()
+    same = bool(np.array_equal(out["obj"][:K].cpu().numpy().view(np.int64), obj.view(np.int64)))
+    s.close()
+    piv = float(cnt[cnt > 0].sum())
+    med = float(np.median(ts))
+    return {"lps": K, "replayed": int((st == 0).sum()), "pivots": int(piv), "stride": stride,
+            "record_kernel_ms": round(rec_ms, 4), "replay_kernel_ms": _stats(ts), "fused_kernel_ms": round(fused_ms, 4),
+            "replay_over_fused": round(med / fused_ms, 4), "search_share_of_fused": round(1.0 - med / fused_ms, 4),
+            "replay_fma_tflops": round(piv * 2.0 * entries / (med / 1e3) / 1e12, 3),
+            "obj_identical_to_solve": same,
+            "note": "replay: Steps 1 and 2 read from the record; load, exchanges, division, update, extraction kept"}
+
+
+def host_cpu() -> dict:
+    """The host's logical CPU count and model (the oracle's cores)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_single_core(C: int) -> dict | None:
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1)
+    over the first C LPs of the headline batch, repeated for about 2 s."""
+    import subprocess
+    code = ("import time, numpy as np, lpgen, oracle\n"
+            f"b = lpgen.config(2, np.arange({C}))\n"
+            "reps, dt = 0, 0.0\n"
+            "while reps < 1 or dt < 2.0:\n"
+            "    t = time.perf_counter(); oracle.solve_batch(b); dt += time.perf_counter() - t; reps += 1\n"
+            f"print({C} * reps / dt)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=300)
+        return {"value": round(float(r.stdout.strip().splitlines()[-1]), 1), "unit": "LPs/s", "cores": 1,
+                "sample": f"first {C} LPs of the headline batch, one thread"}
+    except Exception as e:  # reported, never fatal to the bench line
+        log(f"single-core oracle: {e}")
+        return None
 
 
 def rate_host_resident(blp, torch, hb, ref_obj, steps=3):

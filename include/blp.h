@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BLP_ABI_VERSION 3
+#define BLP_ABI_VERSION 4
 
 typedef struct blp_handle_s* blp_handle;
 
@@ -274,6 +274,27 @@ blp_error blp_get_solution_batch(blp_handle h, int32_t* status, int32_t* iters, 
  * After a solve that mem_limit split into chunks: BLP_ERR_STATE. */
 blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, double* dA, double* dl,
                        double* du, void* hip_stream);
+
+/* Pivot trace of the 100 x 100 class's kernel (the 112 x 112 block tile),
+ * to time the rank-1 update of Step 3 (Sec. 4.3) apart from the search of
+ * Steps 1 and 2 (Sec. 4.2).  The batch (DEVICE data) must be uniform, simplex
+ * LPs only, with m + 2 <= 112 and n + 1 <= 112, and the handle's rule LPC.
+ * trace: DEVICE array of count * stride int32, 1 <= stride <= 513; LP k's
+ * record at trace + k * stride is [p, l_0, e_0, ..., l_{p-1}, e_{p-1}]: the
+ * number of pivots, then each pivot's leaving row and entering slot of the
+ * condensed tableau (slot j < n holds structural variable j until a pivot
+ * brings another variable there; the slot takes the leaving variable).
+ * replay == 0: solve the batch and record every LP's pivots (p = -1 if the
+ * LP's data are not finite or its pivots do not fit the stride).
+ * replay != 0: solve the batch taking each pivot from the record instead of
+ * Steps 1 and 2 (an LP with artificial rows or an invalid record gets status
+ * -1 and NaN outputs); for an LP the record run solved to BLP_OPTIMAL the
+ * outputs are bit-identical to that run's.  Outputs as in blp_solve_batch;
+ * the call is a solve for blp_get_solution and blp_backward.  Stream-ordered;
+ * the caller owns `trace`.  Errors: BLP_ERR_ARG (shape, rule, stride, a
+ * handle with mem_limit), as blp_solve_batch otherwise. */
+blp_error blp_pivot_trace(blp_handle h, const blp_batch* batch, const blp_outputs* out, int32_t* trace,
+                          int32_t stride, int32_t replay, void* hip_stream);
 
 /* Number of simplex LPs of the last solve handled by each kernel class:
  * counts[0..n_reg-1] register-tile variants, counts[n_reg] streaming

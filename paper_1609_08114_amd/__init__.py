@@ -32,7 +32,8 @@ ERROR_NAMES = {0: "SUCCESS", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR
 EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy", "blp_last_error",
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
            "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning",
-           "blp_solve_batch_host", "blp_solve_shared", "blp_solve_batch_static", "blp_static_scratch_bytes"]
+           "blp_solve_batch_host", "blp_solve_shared", "blp_solve_batch_static", "blp_static_scratch_bytes",
+           "blp_pivot_trace"]
 
 
 class blp_options(ctypes.Structure):
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.blp_solve_batch_host.argtypes = [vp, P(blp_batch), P(blp_outputs), i32]
         L.blp_solve_shared.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp, P(blp_outputs), vp]
         L.blp_solve_batch_static.argtypes = [vp, P(blp_batch), P(blp_outputs), vp]
+        L.blp_pivot_trace.argtypes = [vp, P(blp_batch), P(blp_outputs), vp, i32, i32, vp]
         L.blp_static_scratch_bytes.argtypes = []
         L.blp_static_scratch_bytes.restype = ctypes.c_size_t
         for f in EXPORTS:
@@ -143,6 +145,12 @@ def blp_solve_batch_static(h, batch: blp_batch, out: blp_outputs, stream: int | 
 
 def blp_static_scratch_bytes() -> int:
     return lib().blp_static_scratch_bytes()
+
+
+def blp_pivot_trace(h, batch: blp_batch, out: blp_outputs | None, trace: int, stride: int, replay: bool,
+                    stream: int | None = None) -> None:
+    _check(h, lib().blp_pivot_trace(h, ctypes.byref(batch), ctypes.byref(out) if out is not None else None, trace,
+                                    stride, 1 if replay else 0, stream))
 
 
 def blp_solve_batch_host(h, batch: blp_batch, out: blp_outputs, chunks: int = 0) -> None:
@@ -331,6 +339,27 @@ class Solver:
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         self._batch = db.c_struct()
         blp_solve_batch(self.h, self._batch, o, st.cuda_stream)
+        self._last = (db, outputs)
+        return outputs
+
+    def pivot_trace(self, db: DeviceBatch, trace, stride: int, replay: bool, stream=None,
+                    outputs: dict | None = None) -> dict:
+        """blp_pivot_trace on a uniform batch: record each LP's pivots into
+        `trace` (int32 device tensor of count * stride) or replay them.
+        Returns device tensors status, iters, obj, x, y."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        K = db.count
+        if outputs is None:
+            outputs = {"status": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                       "iters": torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                       "obj": torch.empty(max(K, 1), dtype=torch.float64, device=dev),
+                       "x": torch.empty(max(int(db.n[0]) * K, 1), dtype=torch.float64, device=dev),
+                       "y": torch.empty(max(int(db.m[0]) * K, 1), dtype=torch.float64, device=dev)}
+        o = blp_outputs(*[_ptr(outputs[k]) for k in ("status", "iters", "obj", "x", "y")])
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._batch = db.c_struct()
+        blp_pivot_trace(self.h, self._batch, o, _ptr(trace), stride, replay, st.cuda_stream)
         self._last = (db, outputs)
         return outputs
 

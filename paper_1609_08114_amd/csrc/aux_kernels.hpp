@@ -61,6 +61,12 @@ const void* shared_kernel_ptr();
 int shared_threads();
 void shared_shape(int* rows, int* cols);
 
+// Pivot trace of the 112 x 112 block tile (simplex_reg.hip): tr 1 records,
+// tr 2 replays; 256 threads per workgroup, one LP per workgroup.
+hipError_t launch_blk_trace(const KParams& P, int grid, hipStream_t s, int tr);
+const void* blk_trace_kernel_ptr(int tr);
+void blk_trace_shape(int* rows, int* cols);
+
 // Streaming kernel (simplex_gm.hip).
 // deep: the launch's bin is known not to be empty: for tableaux of up to 512
 // rows, more loads in flight per lane and on-chip columns in the dynamic LDS

@@ -10,6 +10,8 @@ namespace blp {
 constexpr int ST_OPTIMAL = 0, ST_INFEASIBLE = 1, ST_UNBOUNDED = 2, ST_ITER_LIMIT = 3, ST_NUMERICAL = 4;
 constexpr int ST_INTERNAL = -1;  // an LP reached a kernel it does not fit (scheduling bug)
 constexpr int ID_NONE = 0x7fffffff;
+// pivots a recorded trace may hold per LP (the replay keeps them in LDS)
+constexpr int kTraceMaxPivots = 256;
 
 // Row flag bits kept in LDS per constraint row.
 constexpr unsigned char RF_GE = 1;    // user wrote ">="
@@ -61,6 +63,10 @@ struct KParams {
     int32_t ws_ld;   // leading dimension (rows, multiple of 16)
     int32_t ws_cols; // columns available per slot
     int32_t ws_lds;  // doubles of dynamic LDS for on-chip columns (0: none)
+    // pivot trace of the 112 x 112 block tile: LP k's record at
+    // trace + k * trace_stride is [count, row 0, slot 0, row 1, slot 1, ...]
+    int32_t* trace;
+    int32_t trace_stride;
     // phase cycle counters (only with -DBLP_PHASE_TIMERS; NULL otherwise)
     unsigned long long* timers;
     // entering rule: 0 largest coefficient, 1 random positive coefficient

@@ -1190,6 +1190,63 @@ blp_error blp_solve_batch_static(blp_handle h, const blp_batch* B, const blp_out
 
 size_t blp_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
+blp_error blp_pivot_trace(blp_handle h, const blp_batch* B, const blp_outputs* out, int32_t* trace, int32_t stride,
+                          int32_t replay, void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (!B) return fail(h, BLP_ERR_ARG, "batch is NULL");
+    if (B->count < 0 || B->count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    if (stride < 1 || stride > 1 + 2 * kTraceMaxPivots)
+        return fail(h, BLP_ERR_ARG, "stride %d outside [1, %d]", stride, 1 + 2 * kTraceMaxPivots);
+    if (!B->uniform) return fail(h, BLP_ERR_ARG, "the pivot trace needs a uniform batch");
+    if (h->opt.pivot_rule != BLP_RULE_LPC) return fail(h, BLP_ERR_ARG, "the pivot trace needs the rule LPC");
+    if (h->opt.mem_limit > 0) return fail(h, BLP_ERR_ARG, "the pivot trace does not split a batch (mem_limit)");
+    const int64_t K = B->count;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    h->solved = false;
+    if (K == 0) {
+        h->count = 0;
+        h->solved = true;
+        return BLP_SUCCESS;
+    }
+    if (!trace) return fail(h, BLP_ERR_ARG, "trace is NULL");
+    if (!B->m || !B->n || !B->kind) return fail(h, BLP_ERR_ARG, "m, n and kind are required");
+    int rows = 0, cols = 0;
+    blk_trace_shape(&rows, &cols);
+    if (B->kind[0] != 0) return fail(h, BLP_ERR_ARG, "the pivot trace needs simplex LPs");
+    if (B->m[0] < 1 || B->n[0] < 1 || B->m[0] + 2 > rows || B->n[0] + 1 > cols)
+        return fail(h, BLP_ERR_ARG, "the pivot trace needs 1 <= m <= %d and 1 <= n <= %d", rows - 2, cols - 1);
+    HIP_TRY(h, begin_call(h, s));
+    SolvePlan sp;
+    blp_error e = prepare(h, B, out, s, sp);
+    if (e != BLP_SUCCESS) return e;
+    // one persistent launch over the identity list (no binning), the grid the
+    // occupancy allows
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, blk_trace_kernel_ptr(replay ? 2 : 1), 256, 0) !=
+            hipSuccess ||
+        occ < 1)
+        occ = 1;
+    KParams Q = sp.P;
+    Q.list = nullptr;
+    Q.direct = 0;
+    Q.bin = 0;
+    Q.trace = trace;
+    Q.trace_stride = stride;
+    int v = -1;  // the registered variant of this tile, for the per-class figures
+    for (int w = 0; w < h->nreg; ++w)
+        if (std::strcmp(h->variants[w].name, "b4_r112_c112") == 0) v = w;
+    HIP_TRY(h, launch_reset(Q.bin_head, 1, s));
+    if (v >= 0) HIP_TRY(h, h->mark(v, true, s));
+    HIP_TRY(h, launch_blk_trace(Q, (int)std::min<int64_t>((int64_t)occ * h->cu_count, K), s, replay ? 2 : 1));
+    if (v >= 0) HIP_TRY(h, h->mark(v, false, s));
+    HIP_TRY(h, end_call(h, s));
+    sp.direct_v = v;
+    record_solve(h, sp, K);
+    return BLP_SUCCESS;
+}
+
 // ------------------------------------------------ host-resident pipeline
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
                            const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,

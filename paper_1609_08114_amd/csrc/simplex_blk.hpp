@@ -177,7 +177,7 @@ __device__ __forceinline__ int mirror_at(const int (&v)[S], int idx) {
 // which is primal feasible for every objective: only the objective row is
 // rebuilt (d_j = c_{var j} - sum_i c_{basis i} T[i][j], -z in the rhs cell)
 // and phase 2 resumes, so phase 1 runs once per workgroup.
-template <int NW, int GC, int RB, int CB, int WPE, bool SH = false>
+template <int NW, int GC, int RB, int CB, int WPE, bool SH = false, int TR = 0>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 simplex_blk_kernel(KParams P) {
     constexpr int NT = NW * 64;
@@ -201,6 +201,8 @@ simplex_blk_kernel(KParams P) {
     __shared__ int64_t s_cur, s_end;
     __shared__ int s_pending;      // SH: objective handed back to a cold start
     __shared__ double s_sim[3 * NW];  // SH: per-wave sums for the similarity test
+    // TR 2: this LP's recorded pivots (count, then row and slot of each)
+    __shared__ int s_tr[TR == 2 ? 1 + 2 * kTraceMaxPivots : 1];
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -267,6 +269,9 @@ simplex_blk_kernel(KParams P) {
         int k = pop();
         if (k < 0) break;
         BLP_T(t_load0);
+        if constexpr (TR == 1) {  // no count until the LP is extracted
+            if (t == 0) P.trace[(int64_t)k * P.trace_stride] = -1;
+        }
 
         // ------------------------------------------------------------ load
         LpRef L = lp_ref(P, k);
@@ -424,6 +429,27 @@ simplex_blk_kernel(KParams P) {
             lds_barrier();
             continue;
         }
+        if constexpr (TR == 2) {
+            // the LP's recorded pivots into LDS; only LPs without artificial
+            // rows replay (their pivots are all phase-2 pivots)
+            const int32_t* tr = P.trace + (int64_t)k * P.trace_stride;
+            const int cnt = tr[0];
+            const bool ok = nart == 0 && cnt >= 0 && cnt <= kTraceMaxPivots && 1 + 2 * cnt <= P.trace_stride;
+            int badp = 0;
+            for (int i = t; ok && i < 1 + 2 * cnt; i += NT) {
+                const int v = tr[i];
+                s_tr[i] = v;
+                // rows in [0, m), slots in [0, n) (no surplus slots here)
+                badp |= i > 0 && (v < 0 || v >= ((i & 1) ? m : n));
+            }
+            if (badp) atomicOr(&s_bad, 1);
+            lds_barrier();
+            if (!ok || s_bad) {
+                write_numerical<NT>(P, L, k, t, ST_INTERNAL);
+                lds_barrier();
+                continue;
+            }
+        }
         const double w0 = mirror_at(bR, ROW_W);
         dead = 0;
         int mode = nart > 0 ? 1 : 2;
@@ -471,6 +497,7 @@ simplex_blk_kernel(KParams P) {
                     }
                 }
                 if (lane == 0) {
+                    if constexpr (TR == 1) P.trace[(int64_t)k * P.trace_stride] = 2 + 2 * (iters - 1) < P.trace_stride ? iters : -1;
                     P.status[k] = sto;
                     P.iters[k] = iters;
                     P.obj[k] = (sto == ST_OPTIMAL || sto == ST_ITER_LIMIT) ? z
@@ -492,6 +519,15 @@ simplex_blk_kernel(KParams P) {
         int drive_r = 0, buf = 0;
         int e_id = ID_NONE, e = -1;  // entering variable and slot from Step 1
         auto step1 = [&]() __attribute__((always_inline)) {
+            if constexpr (TR == 2) {  // the recorded entering slot
+                if (iters < s_tr[0]) {
+                    e = s_tr[2 + 2 * iters];
+                    e_id = mirror_at(cv, e);
+                } else {
+                    e_id = ID_NONE;
+                }
+                return;
+            }
             double da[CS];  // the active objective row
 #pragma unroll
             for (int q = 0; q < CS; ++q) da[q] = mode == 1 ? dW[q] : dO[q];
@@ -721,7 +757,12 @@ simplex_blk_kernel(KParams P) {
                 fr[q] = i < RP ? v : 0.0;
             }
             if (mode != 3) {
-                l = ratio_regs(m, lane, P.eps_piv, fr, bR, bs, dead, rmin, lv);
+                if constexpr (TR == 2) {  // the recorded leaving row
+                    l = s_tr[1 + 2 * iters];
+                    lv = mirror_at(bs, l);
+                } else {
+                    l = ratio_regs(m, lane, P.eps_piv, fr, bR, bs, dead, rmin, lv);
+                }
                 if (l < 0) {
                     st = mode == 2 ? ST_UNBOUNDED : ST_NUMERICAL;
                     if (SH) continue;  // the tile is untouched (SH clears the slot at the update)
@@ -729,6 +770,13 @@ simplex_blk_kernel(KParams P) {
                 }
             }
             const double pe = mirror_at(fr, l);
+            if constexpr (TR == 1) {  // record (row, slot) of this pivot
+                if (t == 0 && 2 + 2 * iters < P.trace_stride) {
+                    int32_t* tr = P.trace + (int64_t)k * P.trace_stride;
+                    tr[1 + 2 * iters] = l;
+                    tr[2 + 2 * iters] = e_piv;
+                }
+            }
             BLP_T(t_p2b);
             BLP_TACC(TM_RTEST, t_p2, t_p2b);
             // Step 3's new pivot row.  The owners of row l (GC lanes of one

@@ -426,6 +426,26 @@ static const void* kernel_ptr_lane() {
     return reinterpret_cast<const void*>(&simplex_lane_kernel<R, C, NWV, WPE>);
 }
 
+// Pivot trace of the 112 x 112 block tile (the kernel of the 100 x 100
+// workload): tr 1 records each pivot's (row, slot), tr 2 replays a recorded
+// sequence with Steps 1 and 2 replaced by reading it (the rank-1 updates, the
+// column and row exchanges and the division stay as they are).
+hipError_t launch_blk_trace(const KParams& P, int grid, hipStream_t s, int tr) {
+    if (tr == 1)
+        hipLaunchKernelGGL((simplex_blk_kernel<4, 16, 7, 7, 2, false, 1>), dim3(grid), dim3(256), 0, s, P);
+    else
+        hipLaunchKernelGGL((simplex_blk_kernel<4, 16, 7, 7, 2, false, 2>), dim3(grid), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+const void* blk_trace_kernel_ptr(int tr) {
+    return tr == 1 ? reinterpret_cast<const void*>(&simplex_blk_kernel<4, 16, 7, 7, 2, false, 1>)
+                   : reinterpret_cast<const void*>(&simplex_blk_kernel<4, 16, 7, 7, 2, false, 2>);
+}
+void blk_trace_shape(int* rows, int* cols) {
+    *rows = 112;
+    *cols = 112;
+}
+
 // Shared-constraint mode (one A, b; many objectives): the block kernel with a
 // 112 x 112 tile.
 constexpr int kSharedRows = 112, kSharedCols = 112;
