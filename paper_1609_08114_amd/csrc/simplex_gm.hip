@@ -302,8 +302,10 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             const bool skip_art = mode == 2;
             auto updated = [&](int j) { return j == e || j == RHS || !(skip_art && S.colvar[j] >= id_lim); };
             // On-chip columns (a wave takes every NW-th slot).
-            for (int j = wave; j < JL; j += NW) {
-                if (!updated(j)) continue;
+            // (run while a step's HBM loads are in flight, spread over the
+            // wave's HBM steps; the rest after them)
+            auto onchip_col = [&](int j) {
+                if (!updated(j)) return;
                 const bool je = j == e;
                 const double pj = S.p[j];
                 double* const col = S.T + j * ldl;
@@ -318,7 +320,8 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                         if (j == RHS) S.b[i] = w;
                     }
                 }
-            }
+            };
+            int jl = wave;  // this wave's next on-chip column
             // HBM columns.  A wave streams U columns per step (j0 + u NW),
             // all their loads issued before any is used: with one column per
             // step each wave had QM loads in flight and the update was bound
@@ -340,6 +343,10 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                 constexpr int UL = U * QM / QL;
                 const int qa = act >> 6;  // the active row's chunk and lane
                 const bool lane_act = lane == (act & 63);
+                // the wave's on-chip columns spread over its HBM steps
+                const int nsteps = C - JL - wave > 0 ? (C - JL - wave + NW * UL - 1) / (NW * UL) : 0;
+                const int ncols = JL - wave > 0 ? (JL - wave + NW - 1) / NW : 0;
+                const int per = nsteps > 0 ? (ncols + nsteps - 1) / nsteps : 0;
                 for (int j0 = JL + wave; j0 < C; j0 += NW * UL) {
                     bool live[UL];
                     double pj[UL], v[UL][QL];
@@ -358,6 +365,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
                                 __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(wsr, (int)o, 0, 0));
                         }
                     }
+                    for (int b = 0; b < per && jl < JL; ++b, jl += NW) onchip_col(jl);
                     // straight-line update and stores; the mirrors' entries
                     // are picked out with selects and written afterwards
                     double wa[UL], wr[QL];
@@ -400,6 +408,7 @@ __global__ void __launch_bounds__(NW * 64) simplex_gm_kernel(KParams P) {
             } else {
                 hbm_update(std::integral_constant<int, QM>{});
             }
+            for (; jl < JL; jl += NW) onchip_col(jl);
             if (t == 0) {
                 S.colvar[e] = S.basis[l];
                 S.basis[l] = e_id;
