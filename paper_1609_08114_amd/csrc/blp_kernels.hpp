@@ -92,10 +92,11 @@ __device__ __forceinline__ void lds_barrier() {
 // 2 entering-column publish, 3 ratio test + pivot-row division + barrier,
 // 4 pivot update, 5 extraction, 6 pivots, 7 LPs; block-tile kernel only:
 // 8 ratio test alone, 9 pivot-row division in the owning wave, 10 pivots
-// whose row wave 0 owns.
+// whose row wave 0 owns; 11 the load up to the rows' preparation, 12 from
+// there to the finished tile (block-tile kernel).
 enum {
     TM_LOAD = 0, TM_PRICE, TM_PUBCOL, TM_RATIO, TM_PIVOT, TM_EXTRACT, TM_PIVOTS, TM_LPS,
-    TM_RTEST, TM_DIV, TM_DIVN, TM_SLOTS
+    TM_RTEST, TM_DIV, TM_DIVN, TM_LD_ROWS, TM_LD_TILE, TM_SLOTS
 };
 #ifdef BLP_PHASE_TIMERS
 #define BLP_TDECL unsigned long long tm_acc_[TM_SLOTS] = {}

@@ -379,7 +379,8 @@ void blp_destroy(blp_handle h) {
         (void)hipMemcpy(t, h->timers, sizeof t, hipMemcpyDeviceToHost);
         fprintf(stderr,
                 "[blp timers] LPs %llu pivots %llu | cycles per LP: load %.0f extract %.0f | per pivot: price %.0f "
-                "pubcol %.0f ratio %.0f pivot %.0f | ratio test %.0f, division %.0f over %llu owned pivots\n",
+                "pubcol %.0f ratio %.0f pivot %.0f | ratio test %.0f, division %.0f over %llu owned pivots | "
+                "load: rows %.0f, tile %.0f\n",
                 t[TM_LPS], t[TM_PIVOTS], t[TM_LPS] ? (double)t[TM_LOAD] / t[TM_LPS] : 0.0,
                 t[TM_LPS] ? (double)t[TM_EXTRACT] / t[TM_LPS] : 0.0,
                 t[TM_PIVOTS] ? (double)t[TM_PRICE] / t[TM_PIVOTS] : 0.0,
@@ -387,7 +388,8 @@ void blp_destroy(blp_handle h) {
                 t[TM_PIVOTS] ? (double)t[TM_RATIO] / t[TM_PIVOTS] : 0.0,
                 t[TM_PIVOTS] ? (double)t[TM_PIVOT] / t[TM_PIVOTS] : 0.0,
                 t[TM_PIVOTS] ? (double)t[TM_RTEST] / t[TM_PIVOTS] : 0.0,
-                t[TM_DIVN] ? (double)t[TM_DIV] / t[TM_DIVN] : 0.0, t[TM_DIVN]);
+                t[TM_DIVN] ? (double)t[TM_DIV] / t[TM_DIVN] : 0.0, t[TM_DIVN],
+                t[TM_LPS] ? (double)t[TM_LD_ROWS] / t[TM_LPS] : 0.0, t[TM_LPS] ? (double)t[TM_LD_TILE] / t[TM_LPS] : 0.0);
         (void)hipFree(h->timers);
     }
 #endif

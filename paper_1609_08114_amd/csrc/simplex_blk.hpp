@@ -334,6 +334,8 @@ simplex_blk_kernel(KParams P) {
             }
         }
         lds_barrier();
+        BLP_T(t_ld1);
+        BLP_TACC(TM_LD_ROWS, t_load0, t_ld1);
         if (t < 64) scan_art_rows(m, lane, s_flag, s_artrow, s_rank, &s_nart);
         lds_barrier();
         const int nart = __builtin_amdgcn_readfirstlane(s_nart);
@@ -408,6 +410,11 @@ simplex_blk_kernel(KParams P) {
                 for (int r = 0; r < RB; ++r) __asm__ volatile("" : "+v"(T[r][c]));
             __asm__ volatile("" : "+v"(bad));
         }
+#ifdef BLP_PHASE_TIMERS
+        __builtin_amdgcn_s_waitcnt(0);  // the tile's loads have returned
+        BLP_T(t_ld2);
+        BLP_TACC(TM_LD_TILE, t_ld1, t_ld2);
+#endif
         // register mirrors (identical in every wave)
 #pragma unroll
         for (int q = 0; q < CS; ++q) {
