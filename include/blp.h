@@ -236,11 +236,14 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_o
  * rebuilt); other objectives, or every objective when the directions are
  * unrelated, are solved from scratch.  Iteration counts and, at degenerate
  * optima, x and y may therefore differ from independent solves; statuses and
- * optima do not.  Needs m + 2 <= 112 and
- * n + n_art + 1 <= 112 (n_art = rows whose "<=" form has a negative rhs),
- * else BLP_ERR_TOO_LARGE.  A handle whose options force a register-tile
- * variant (variant >= 0) runs the cold solves with that variant, and fails
- * with BLP_ERR_TOO_LARGE if it cannot hold them.  Reads b, sense and the first 65 objectives back
+ * optima do not.  Warm starts need m + 2 <= 112 and n + n_art + 1 <= 112
+ * (n_art = rows whose "<=" form has a negative rhs); larger constraint sets,
+ * up to the limits of blp_solve_batch (m <= 2046, n + m + 1 <= 4096, else
+ * BLP_ERR_TOO_LARGE), are solved from scratch for every objective by the
+ * smallest register-tile variant that holds them, else the streaming kernel.
+ * A handle whose options force a register-tile variant (variant >= 0) runs
+ * the cold solves with that variant, and fails with BLP_ERR_TOO_LARGE if it
+ * cannot hold them.  Reads b, sense and the first 65 objectives back
  * to the host once (synchronising the stream); the solve itself is ordered
  * on the stream.
  * The handle keeps no results of this call (blp_backward and

@@ -1260,10 +1260,10 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     if (!A || !b || !sense) return fail(h, BLP_ERR_ARG, "A, b and sense are required");
     if (count > 0 && (!C || !out || !out->status || !out->iters || !out->obj || !out->x || !out->y))
         return fail(h, BLP_ERR_ARG, "C and all five output buffers are required");
+    if (m > kMaxM || (int64_t)n + m + 1 > kMaxCols)
+        return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need m <= %d and n + m + 1 <= %d", kMaxM, kMaxCols);
     int rows = 0, cols = 0;
     shared_shape(&rows, &cols);
-    if (m + 2 > rows || n + 1 > cols)
-        return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need m + 2 <= %d and n + n_art + 1 <= %d", rows, cols);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
     HIP_TRY(h, begin_call(h, s));
@@ -1289,11 +1289,10 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
         }
         close += dot > 0.9 * std::sqrt(aa * bb);
     }
-    const bool warm = ns > 1 && 2 * close >= ns - 1;
     int nart = 0;
     for (int i = 0; i < m; ++i) nart += (hs[i] ? -hb[i] : hb[i]) < 0.0;
-    if (n + nart + 1 > cols)
-        return fail(h, BLP_ERR_TOO_LARGE, "shared constraints need n + n_art + 1 <= %d (n_art = %d)", cols, nart);
+    // warm starts need the shared tile; larger sets take the cold route
+    const bool warm = ns > 1 && 2 * close >= ns - 1 && m + 2 <= rows && n + nart + 1 <= cols;
     if (count == 0) return BLP_SUCCESS;
     KParams P{};
     P.count = count;
@@ -1325,9 +1324,12 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     P.bin_head = h->shared_ctr.as<int32_t>();
     P.bin = 0;
     if (!warm) {
-        // unrelated directions: every objective is a cold solve, by the
-        // first register kernel of the same tile (or the forced variant),
-        // every LP reading the one constraint set
+        // unrelated directions, or constraints beyond the shared tile: every
+        // objective is a cold solve, every LP reading the one constraint set.
+        // They all have the same tableau shape (the artificial rows come from
+        // b and sense), so one kernel takes them all: the forced variant, else
+        // the register variant of smallest area that holds the shape (the
+        // shared tile's shape first), else the streaming kernel.
         int v = -1;
         if (h->opt.variant >= 0) {
             v = h->opt.variant;
@@ -1337,12 +1339,51 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
                             h->variants[v].name);
         }
         for (int i = 0; i < h->nreg && v < 0; ++i)
-            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols && !h->variants[i].type1_only)
+            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols && !h->variants[i].type1_only &&
+                m + 2 <= rows && n + nart + 1 <= cols)
                 v = i;
-        if (v < 0) return fail(h, BLP_ERR_STATE, "no register variant of the shared tile shape");
-        P.shared_in = 1;
-        HIP_TRY(h, launch_reset(P.bin_head, 1, s));
-        HIP_TRY(h, h->variants[v].launch(P, reg_grid(h, v, count), s));
+        long barea = -1;
+        for (int i = 0; i < h->nreg && h->opt.variant < 0 && (v < 0 || barea >= 0); ++i) {
+            const RegVariant& rv = h->variants[i];
+            if (rv.max_rows >= m + 2 && rv.max_cols >= n + nart + 1 && !rv.type1_only) {
+                const long a = (long)rv.max_rows * rv.max_cols;
+                if (barea < 0 || a < barea) {
+                    barea = a;
+                    v = i;
+                }
+            }
+        }
+        if (v >= 0) {
+            P.shared_in = 1;
+            HIP_TRY(h, launch_reset(P.bin_head, 1, s));
+            HIP_TRY(h, h->variants[v].launch(P, reg_grid(h, v, count), s));
+            HIP_TRY(h, end_call(h, s));
+            return BLP_SUCCESS;
+        }
+        // the streaming kernel, its workspace and LDS planned as for a
+        // uniform batch of this shape
+        const int32_t km = m, kn = n, kk = 0;
+        blp_batch B{};
+        B.count = count;
+        B.uniform = 1;
+        B.m = &km;
+        B.n = &kn;
+        B.kind = &kk;
+        B.A = A;
+        B.b = b;
+        B.sense = sense;
+        B.c = C;
+        SolvePlan sp;
+        blp_error pe = prepare(h, &B, out, s, sp);
+        if (pe != BLP_SUCCESS) return pe;
+        KParams Q = sp.P;
+        Q.shared_in = 1;
+        Q.list = nullptr;
+        Q.direct = 0;
+        Q.bin = 0;
+        Q.bin_head = P.bin_head;
+        HIP_TRY(h, launch_reset(Q.bin_head, 1, s));
+        HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, count), sp.gm_lds, s, sp.gm_deep));
         HIP_TRY(h, end_call(h, s));
         return BLP_SUCCESS;
     }

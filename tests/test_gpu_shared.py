@@ -194,18 +194,37 @@ def test_cold_route_on_every_register_variant():
         assert (o["status"] == oracle.OPTIMAL).any()
 
 
+def test_beyond_the_shared_tile():
+    """Constraint sets larger than the 112 x 112 tile of the warm-start
+    kernel take the cold route: a 130 x 130 type-1 set in the register tile
+    that holds it, and workload 3's first 200 x 200 set (rows of both senses,
+    phase 1) in the streaming kernel; every objective against the oracle."""
+    rng = np.random.default_rng(31)
+    m = n = 130
+    A = rng.uniform(1.0, 10.0, size=(m, n))
+    b = rng.uniform(10.0, 100.0, size=m)
+    C = rng.normal(size=(120, n))
+    C[:60] = np.abs(C[:60])  # half of them in the positive orthant
+    _check(A, b, np.zeros(m, np.int8), C, "shared-130")
+    h3 = lpgen.config(3, range(0, 1))
+    m3, n3 = int(h3.m[0]), int(h3.n[0])
+    A3 = h3.A[:m3 * n3].reshape(m3, n3)
+    C3 = np.vstack([h3.c[:n3], rng.uniform(1.0, 10.0, size=(15, n3))])
+    _check(A3, h3.b[:m3], h3.sense[:m3], C3, "shared-200-streaming")
+
+
 def test_shared_errors():
     import torch
 
     import paper_1609_08114_amd as blp
     s = blp.Solver()
     dev = torch.device("cuda")
-    A = torch.ones(200 * 5, dtype=torch.float64, device=dev)
-    b = torch.ones(200, dtype=torch.float64, device=dev)
-    sense = torch.zeros(200, dtype=torch.int8, device=dev)
+    A = torch.ones(2100 * 5, dtype=torch.float64, device=dev)
+    b = torch.ones(2100, dtype=torch.float64, device=dev)
+    sense = torch.zeros(2100, dtype=torch.int8, device=dev)
     C = torch.ones(3, 5, dtype=torch.float64, device=dev)
     with pytest.raises(blp.BlpError) as ei:
-        s.solve_shared(A, b, sense, C)
+        s.solve_shared(A, b, sense, C)  # more rows than any LP may have
     assert ei.value.code == blp.BLP_ERR_TOO_LARGE
     out = s.solve_shared(A[:10], b[:2], sense[:2], C[:0])
     torch.cuda.synchronize()
