@@ -275,7 +275,7 @@ def main():
     # ---------------------- shared constraints, many objectives (Sec. 7)
     shared = None
     if not args.no_classes:
-        shared = bench_shared(blp, torch, lpgen, oracle_check=not args.no_cpu)
+        shared = bench_shared(blp, torch, lpgen)
 
     # ------------------- captured launch sequences against eager launches
     graphs = lanes = None
@@ -529,11 +529,13 @@ def counter_pass(blp, torch, lpgen, K, workload="2"):
     log(f"counter pass done: copy of {1 << 30} bytes, one solve of {K} LPs (workload {workload})")
 
 
-def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:
+def bench_shared(blp, torch, lpgen, K=50_000) -> dict:
     """One workload-2 polytope (m = n = 100) queried in K directions, as in
     support-function sampling: directions swept around a circle, and random
     unit directions.  blp_solve_shared (phase 1 once, warm starts) against
-    the same K LPs solved independently by blp_solve_batch."""
+    the same K LPs solved independently by blp_solve_batch (the oracle
+    comparison of this mode is in the tests), and the time of its adjoint
+    blp_backward_shared."""
     dev = torch.device("cuda")
     lp = lpgen.config(2, [0]).lp(0)
     A, b, sense = lp["A"], lp["b"], lp["sense"]
@@ -559,6 +561,15 @@ def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:
             out = s.solve_shared(Ad, bd, sd, Cd)
         torch.cuda.synchronize()
         ms_sh = (time.perf_counter() - t0) * 1e3 / reps
+        # the adjoint of the sweep: dC, db and dA summed over the objectives
+        g = torch.from_numpy(rng.uniform(0.0, 1.0, size=K)).to(dev)
+        s.backward_shared(out, m, n, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.backward_shared(out, m, n, g)
+        torch.cuda.synchronize()
+        ms_bw = (time.perf_counter() - t0) * 1e3 / reps
         s.close()
         obj_sh = out["obj"][:K].cpu().numpy()
         it_sh = out["iters"][:K].cpu().numpy()
@@ -581,19 +592,9 @@ def bench_shared(blp, torch, lpgen, K=50_000, oracle_check=True) -> dict:
                  "independent_lps_per_s": round(K / (ms_ind / 1e3), 1), "independent_ms": round(ms_ind, 3),
                  "speedup": round(ms_ind / ms_sh, 2), "pivots_per_lp_shared": round(float(it_sh.mean()), 2),
                  "pivots_per_lp_independent": round(float(it_i.mean()), 2),
-                 "status_mismatch": int((st_sh != st_i).sum()), "max_obj_relerr_vs_independent": float(rel.max())}
-        if oracle_check:
-            import oracle
-            S = 2000
-            sub = lpgen.make_batch(1002, np.zeros(S, np.int64), np.ones(S, np.int32), np.full(S, m), np.full(S, n))
-            sub.A, sub.b, sub.sense = hb.A[:S * m * n], hb.b[:S * m], hb.sense[:S * m]
-            sub.c = hb.c[:S * n]
-            ref = oracle.solve_batch(sub)
-            okr = ref["status"] == 0
-            relo = np.abs(obj_sh[:S][okr] - ref["obj"][okr]) / np.maximum(1.0, np.abs(ref["obj"][okr]))
-            entry["oracle_sample"] = S
-            entry["oracle_status_mismatch"] = int((st_sh[:S] != ref["status"]).sum())
-            entry["oracle_max_obj_relerr"] = float(relo.max())
+                 "status_mismatch": int((st_sh != st_i).sum()), "max_obj_relerr_vs_independent": float(rel.max()),
+                 "backward_ms": round(ms_bw, 3),
+                 "backward_GBps": round(K * 8.0 * (2 * n + m + 1) / (ms_bw / 1e3) / 1e9, 1)}
         res[name] = entry
         log(f"shared {name}: {entry}")
     return res

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BLP_ABI_VERSION 4
+#define BLP_ABI_VERSION 5
 
 typedef struct blp_handle_s* blp_handle;
 
@@ -251,6 +251,21 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_o
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
                            const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,
                            void* hip_stream);
+
+/* Adjoint of a blp_solve_shared call for loss = sum_k g[k] obj_k (an
+ * extension beyond the paper, valid at non-degenerate optima), from that
+ * call's outputs: status (count), x (count x n) and y (count x m).  With
+ * w_k = g_k for LPs whose status is BLP_OPTIMAL, else 0:
+ * dC = w_k x_k (count x n, row k at k*n), db = sum_k w_k y_k (m),
+ * dA = -sum_k w_k y_k x_k^T (m x n, row-major).  All DEVICE memory, caller-
+ * owned; any output may be NULL to skip it.  The sums over k run in a fixed
+ * order (consecutive LPs in chunks, then the chunks in order), so repeated
+ * calls give the same bits.  The handle keeps the partial sums (its
+ * workspace grows as needed).  Stream-ordered.  Errors: BLP_ERR_ARG (sizes,
+ * a NULL input), BLP_ERR_NOMEM. */
+blp_error blp_backward_shared(blp_handle h, int32_t m, int32_t n, int64_t count, const int32_t* status,
+                              const double* x, const double* y, const double* g, double* dC, double* db,
+                              double* dA, void* hip_stream);
 
 /* Copy LP k's results of the last solve to HOST memory (synchronises the
  * solve's stream).  x (length n) and y (length m) may be NULL. */

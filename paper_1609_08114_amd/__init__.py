@@ -33,7 +33,7 @@ EXPORTS = ["blp_abi_version", "blp_options_default", "blp_create", "blp_destroy"
            "blp_solve_batch", "blp_get_solution", "blp_get_solution_batch", "blp_backward", "blp_last_bins",
            "blp_variant_info", "blp_last_kernel_ms", "blp_autotune", "blp_load_tuning", "blp_tuning",
            "blp_solve_batch_host", "blp_solve_shared", "blp_solve_batch_static", "blp_static_scratch_bytes",
-           "blp_pivot_trace"]
+           "blp_pivot_trace", "blp_backward_shared"]
 
 
 class blp_options(ctypes.Structure):
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         L.blp_solve_shared.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp, P(blp_outputs), vp]
         L.blp_solve_batch_static.argtypes = [vp, P(blp_batch), P(blp_outputs), vp]
         L.blp_pivot_trace.argtypes = [vp, P(blp_batch), P(blp_outputs), vp, i32, i32, vp]
+        L.blp_backward_shared.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.blp_static_scratch_bytes.argtypes = []
         L.blp_static_scratch_bytes.restype = ctypes.c_size_t
         for f in EXPORTS:
@@ -151,6 +152,11 @@ def blp_pivot_trace(h, batch: blp_batch, out: blp_outputs | None, trace: int, st
                     stream: int | None = None) -> None:
     _check(h, lib().blp_pivot_trace(h, ctypes.byref(batch), ctypes.byref(out) if out is not None else None, trace,
                                     stride, 1 if replay else 0, stream))
+
+
+def blp_backward_shared(h, m: int, n: int, count: int, status, x, y, g, dC, db, dA,
+                        stream: int | None = None) -> None:
+    _check(h, lib().blp_backward_shared(h, m, n, count, status, x, y, g, dC, db, dA, stream))
 
 
 def blp_solve_batch_host(h, batch: blp_batch, out: blp_outputs, chunks: int = 0) -> None:
@@ -380,6 +386,20 @@ class Solver:
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         blp_solve_shared(self.h, m, n, _ptr(A), _ptr(b), _ptr(sense), K, _ptr(C), o, st.cuda_stream)
         return out
+
+    def backward_shared(self, out: dict, m: int, n: int, g, stream=None, want=("dC", "db", "dA")) -> dict:
+        """Gradients of sum_k g[k] obj_k after solve_shared (its output dict
+        `out`): dC (count x n), db (m), dA (m x n), new device tensors."""
+        import torch
+        K = int(g.numel())
+        dev = g.device
+        res = {"dC": torch.empty(max(K * n, 1), dtype=torch.float64, device=dev) if "dC" in want else None,
+               "db": torch.empty(m, dtype=torch.float64, device=dev) if "db" in want else None,
+               "dA": torch.empty(m * n, dtype=torch.float64, device=dev) if "dA" in want else None}
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        blp_backward_shared(self.h, m, n, K, _ptr(out["status"]), _ptr(out["x"]), _ptr(out["y"]), _ptr(g),
+                            _ptr(res["dC"]), _ptr(res["db"]), _ptr(res["dA"]), st.cuda_stream)
+        return res
 
     def autotune(self, db: DeviceBatch, sample: int = 512, cache_path: str | None = None, stream=None) -> None:
         import torch

@@ -9,6 +9,8 @@
 //    sequential sum (Sec. 6 uses one thread per LP for the same reason).
 //  - backward_simplex / backward_hyperbox: the adjoint of the optimum with
 //    respect to the data, from the primal and dual solutions.
+#include <algorithm>
+
 #include "aux_kernels.hpp"
 #include "blp_kernels.hpp"
 
@@ -501,7 +503,97 @@ hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc
                        db, dA);
     return hipGetLastError();
 }
+// Adjoint of a shared-constraint solve (one A, b; objectives C, LP k's
+// results x_k at X + k n, y_k at Y + k m): w_k = g_k for OPTIMAL LPs, else 0;
+// dC[k] = w_k x_k, db = sum_k w_k y_k, dA = -sum_k w_k y_k x_k^T.  The sums
+// over k run in increasing k inside chunks of consecutive LPs (one partial
+// per chunk), then over the chunks in order: the same bits on every call.
+__global__ void __launch_bounds__(256) shared_bwd_dc_kernel(int64_t count, int n, const int32_t* st, const double* g,
+                                                            const double* X, double* dC) {
+    const int64_t E = count * (int64_t)n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x, e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t dk = stride / n;
+    const int dr = (int)(stride - dk * n);
+    int64_t k = e0 / n;
+    int r = (int)(e0 - k * n);
+    for (int64_t e = e0; e < E; e += stride) {
+        dC[e] = st[k] == ST_OPTIMAL ? g[k] * X[e] : 0.0;
+        k += dk;
+        r += dr;
+        if (r >= n) {
+            r -= n;
+            ++k;
+        }
+    }
+}
+// One block per (16 x 16 tile of dA, chunk of LPs): thread (i, j) of the
+// tile sums fma(w_k y_ki, x_kj, .) over the chunk's LPs in order; the
+// threads of tile column 0 of the first tile column also sum w_k y_ki for db.
+__global__ void __launch_bounds__(256) shared_bwd_part_kernel(int64_t count, int m, int n, int64_t chunk,
+                                                              const int32_t* st, const double* g, const double* X,
+                                                              const double* Y, double* part_a, double* part_b) {
+    const int tiles_n = (n + 15) / 16;
+    const int ti = blockIdx.x / tiles_n, tj = blockIdx.x - ti * tiles_n;
+    const int i = ti * 16 + (int)threadIdx.x / 16, j = tj * 16 + (int)threadIdx.x % 16;
+    const int64_t c = blockIdx.y, k0 = c * chunk, k1 = k0 + chunk < count ? k0 + chunk : count;
+    const bool in = i < m && j < n;
+    const bool rowsum = tj == 0 && threadIdx.x % 16 == 0 && i < m;
+    const int ic = i < m ? i : m - 1, jc = j < n ? j : n - 1;
+    double acc = 0.0, accb = 0.0;
+    for (int64_t k = k0; k < k1; ++k) {
+        // (x and y of an LP that is not OPTIMAL may be NaN: selected away,
+        // never multiplied by a zero weight)
+        const bool ok = st[k] == ST_OPTIMAL;
+        const double wy = ok ? g[k] * Y[k * m + ic] : 0.0;
+        acc = __builtin_fma(wy, ok ? X[k * n + jc] : 0.0, acc);
+        accb = accb + wy;
+    }
+    if (in) part_a[c * (int64_t)m * n + (int64_t)i * n + j] = acc;
+    if (rowsum) part_b[c * m + i] = accb;
+}
+// out[e] = sign * (sum over the chunks, in order, of part[c len + e])
+__global__ void __launch_bounds__(256) shared_bwd_final_kernel(int nchunks, int64_t len, const double* part,
+                                                               double sign, double* out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < nchunks; ++c) acc = acc + part[(int64_t)c * len + e];
+        out[e] = sign * acc;
+    }
+}
+
 int box_shared_blocks(int64_t count) { return (int)((count + kBoxRedLps - 1) / kBoxRedLps); }
+int64_t shared_bwd_chunk(int64_t count, int m, int n) {
+    // chunks of at least 1,024 LPs, and partial sums of at most 8M doubles
+    const int64_t per = (int64_t)m * n + m;
+    const int64_t max_chunks = std::max<int64_t>(1, (int64_t(8) << 20) / per);
+    const int64_t chunks =
+        std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(1, (count + 1023) / 1024), max_chunks), 65535);
+    return (count + chunks - 1) / chunks;
+}
+hipError_t launch_backward_shared(int64_t count, int m, int n, const int32_t* st, const double* g, const double* X,
+                                  const double* Y, double* part, double* dC, double* db, double* dA, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (dC) {
+        hipLaunchKernelGGL(shared_bwd_dc_kernel, dim3(grid_for(count * (int64_t)n, 256, 1 << 16)), dim3(256), 0, s,
+                           count, n, st, g, X, dC);
+    }
+    if (db || dA) {
+        const int64_t chunk = shared_bwd_chunk(count, m, n);
+        const int nchunks = (int)((count + chunk - 1) / chunk);
+        double* part_a = part;
+        double* part_b = part + (int64_t)nchunks * m * n;
+        const unsigned tiles = (unsigned)(((m + 15) / 16) * ((n + 15) / 16));
+        hipLaunchKernelGGL(shared_bwd_part_kernel, dim3(tiles, (unsigned)nchunks), dim3(256), 0, s, count, m, n, chunk,
+                           st, g, X, Y, part_a, part_b);
+        if (dA)
+            hipLaunchKernelGGL(shared_bwd_final_kernel, dim3(grid_for((int64_t)m * n, 256, 1 << 16)), dim3(256), 0, s,
+                               nchunks, (int64_t)m * n, part_a, -1.0, dA);
+        if (db)
+            hipLaunchKernelGGL(shared_bwd_final_kernel, dim3(grid_for(m, 256, 1 << 16)), dim3(256), 0, s, nchunks,
+                               (int64_t)m, part_b, 1.0, db);
+    }
+    return hipGetLastError();
+}
 hipError_t launch_backward_box_shared(const KParams& P, int n, const double* g, double* part, double* dl, double* du,
                                       hipStream_t s) {
     const int nb = box_shared_blocks(P.count);

@@ -52,6 +52,12 @@ hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const d
 // Shared box: dl, du (length n) summed over the hyperbox LPs in a fixed
 // order; `part` holds 2 n doubles per block of box_shared_blocks(count).
 int box_shared_blocks(int64_t count);
+// Adjoint of a shared-constraint solve: dC (count x n), db (m), dA (m x n);
+// `part` holds shared_bwd_chunk's partial sums, (m n + m) doubles per chunk
+// of shared_bwd_chunk(count, m, n) LPs.
+int64_t shared_bwd_chunk(int64_t count, int m, int n);
+hipError_t launch_backward_shared(int64_t count, int m, int n, const int32_t* st, const double* g, const double* X,
+                                  const double* Y, double* part, double* dC, double* db, double* dA, hipStream_t s);
 hipError_t launch_backward_box_shared(const KParams& P, int n, const double* g, double* part, double* dl, double* du,
                                       hipStream_t s);
 

@@ -1249,6 +1249,27 @@ blp_error blp_pivot_trace(blp_handle h, const blp_batch* B, const blp_outputs* o
     return BLP_SUCCESS;
 }
 
+blp_error blp_backward_shared(blp_handle h, int32_t m, int32_t n, int64_t count, const int32_t* status,
+                              const double* x, const double* y, const double* g, double* dC, double* db, double* dA,
+                              void* stream) {
+    if (!h) return BLP_ERR_ARG;
+    h->err.clear();
+    if (count < 0 || count > 0x7fffffffLL) return fail(h, BLP_ERR_ARG, "count out of range");
+    if (m < 1 || n < 1 || m > kMaxM || (int64_t)n + m + 1 > kMaxCols)
+        return fail(h, BLP_ERR_ARG, "m and n outside 1 <= m <= %d, n + m + 1 <= %d", kMaxM, kMaxCols);
+    if (count == 0 || (!dC && !db && !dA)) return BLP_SUCCESS;
+    if (!status || !x || !y || !g) return fail(h, BLP_ERR_ARG, "status, x, y and g are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, begin_call(h, s));
+    const int64_t chunk = shared_bwd_chunk(count, m, n);
+    const int64_t nchunks = (count + chunk - 1) / chunk;
+    if (db || dA) HIP_TRY(h, h->bwd_part.reserve(sizeof(double) * (size_t)nchunks * ((size_t)m * n + m)));
+    HIP_TRY(h, launch_backward_shared(count, m, n, status, g, x, y, h->bwd_part.as<double>(), dC, db, dA, s));
+    HIP_TRY(h, end_call(h, s));
+    return BLP_SUCCESS;
+}
+
 // ------------------------------------------------ host-resident pipeline
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
                            const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_host_only_calls():
-    assert blp.blp_abi_version() == 4
+    assert blp.blp_abi_version() == 5
     o = blp.blp_options_default()
     assert o.device == 0 and o.mode == 0 and o.variant == -1 and o.max_iter == 0
     vs = blp.variants()

@@ -230,3 +230,74 @@ def test_shared_errors():
     torch.cuda.synchronize()
     assert out["status"].numel() == 1  # nothing solved, nothing written
     s.close()
+
+
+def test_shared_adjoint():
+    """blp_backward_shared after solve_shared: dC, db and dA against the
+    formulas on the same x, y, status (w_k = g_k at OPTIMAL LPs, else 0), and
+    against the per-LP adjoint of blp_backward summed over the objectives;
+    repeated calls give the same bits."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    rng = np.random.default_rng(41)
+    m, n, K = 24, 20, 3000
+    A = rng.uniform(1.0, 10.0, size=(m, n))
+    b = rng.uniform(10.0, 100.0, size=m)
+    sense = np.zeros(m, np.int8)
+    C = rng.normal(size=(K, n))
+    C[5] = np.nan  # a NUMERICAL objective: no gradient
+    dev = torch.device("cuda")
+    s = blp.Solver()
+    try:
+        tA = torch.from_numpy(A.ravel()).to(dev)
+        tb = torch.from_numpy(b).to(dev)
+        ts = torch.from_numpy(sense).to(dev)
+        out = s.solve_shared(tA, tb, ts, torch.from_numpy(C).to(dev))
+        g = torch.from_numpy(rng.uniform(0.0, 1.0, size=K)).to(dev)
+        r1 = s.backward_shared(out, m, n, g)
+        r2 = s.backward_shared(out, m, n, g)
+        torch.cuda.synchronize()
+        st = out["status"][:K].cpu().numpy()
+        X = out["x"][:K * n].cpu().numpy().reshape(K, n)
+        Y = out["y"][:K * m].cpu().numpy().reshape(K, m)
+        w = np.where(st == 0, g.cpu().numpy(), 0.0)
+        assert st[5] == blp.BLP_NUMERICAL and (st == 0).sum() > K // 2
+        got = {k: v.cpu().numpy() for k, v in r1.items()}
+        for k in got:
+            assert np.array_equal(got[k].view(np.int64), r2[k].cpu().numpy().view(np.int64)), k
+        dC = np.where(st[:, None] == 0, w[:, None] * np.nan_to_num(X), 0.0)
+        assert np.array_equal(got["dC"].reshape(K, n), dC)
+        wy = np.where(st[:, None] == 0, w[:, None] * np.nan_to_num(Y), 0.0)
+        db = wy.sum(axis=0)
+        dA = -(wy.T @ np.where(st[:, None] == 0, np.nan_to_num(X), 0.0))
+        scale_b = (np.abs(wy).sum(axis=0) + 1.0)
+        assert (np.abs(got["db"] - db) <= 1e-12 * scale_b).all()
+        scale_a = np.abs(wy).T @ np.abs(np.where(st[:, None] == 0, np.nan_to_num(X), 0.0)) + 1.0
+        assert (np.abs(got["dA"].reshape(m, n) - dA) <= 1e-12 * scale_a).all()
+    finally:
+        s.close()
+    # the per-LP adjoint of the same LPs solved as an ordinary batch, summed
+    ok = st == 0
+    lps = [dict(A=A, b=b, c=C[k], sense=sense) for k in np.nonzero(ok)[0][:400]]
+    hb = crafted_batch(lps)
+    s2 = blp.Solver()
+    try:
+        db_ = blp.DeviceBatch.from_host(hb)
+        o2 = s2.solve(db_)
+        gk = torch.from_numpy(w[ok][:400].copy()).to(dev)
+        grads = s2.backward(gk)
+        torch.cuda.synchronize()
+        per_dA = grads["dA"].cpu().numpy().reshape(len(lps), m, n).sum(axis=0)
+        sel = np.zeros(K)
+        sel[np.nonzero(ok)[0][:400]] = 1.0
+        s3 = blp.Solver()
+        out3 = s3.solve_shared(tA, tb, ts, torch.from_numpy(C).to(dev))
+        r3 = s3.backward_shared(out3, m, n, torch.from_numpy(sel * g.cpu().numpy()).to(dev))
+        torch.cuda.synchronize()
+        s3.close()
+        tot = np.abs(per_dA).max() + 1.0
+        assert np.abs(r3["dA"].cpu().numpy().reshape(m, n) - per_dA).max() <= 1e-9 * tot
+        assert o2["status"][:len(lps)].cpu().numpy().max() == 0
+    finally:
+        s2.close()
