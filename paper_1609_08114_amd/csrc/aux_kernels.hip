@@ -526,29 +526,45 @@ __global__ void __launch_bounds__(256) shared_bwd_dc_kernel(int64_t count, int n
         }
     }
 }
-// One block per (16 x 16 tile of dA, chunk of LPs): thread (i, j) of the
-// tile sums fma(w_k y_ki, x_kj, .) over the chunk's LPs in order; the
-// threads of tile column 0 of the first tile column also sum w_k y_ki for db.
+// One block per (16 x 16 tile of dA, chunk of LPs): the block stages 64 LPs
+// at a time in LDS (w_k y_ki for the tile's 16 rows, x_kj for its 16
+// columns; zero for LPs that are not OPTIMAL, whose x and y may be NaN and
+// are selected away rather than multiplied by a zero weight), then thread
+// (i, j) of the tile sums fma(w_k y_ki, x_kj, .) over them in LP order; the
+// tile's first column of threads in the first tile column also sums w_k y_ki
+// for db.
 __global__ void __launch_bounds__(256) shared_bwd_part_kernel(int64_t count, int m, int n, int64_t chunk,
                                                               const int32_t* st, const double* g, const double* X,
                                                               const double* Y, double* part_a, double* part_b) {
+    constexpr int KS = 64;  // LPs per stage
+    __shared__ double s_y[KS][16], s_x[KS][16];
     const int tiles_n = (n + 15) / 16;
     const int ti = blockIdx.x / tiles_n, tj = blockIdx.x - ti * tiles_n;
-    const int i = ti * 16 + (int)threadIdx.x / 16, j = tj * 16 + (int)threadIdx.x % 16;
+    const int il = (int)threadIdx.x / 16, jl = (int)threadIdx.x % 16;
+    const int i = ti * 16 + il, j = tj * 16 + jl;
     const int64_t c = blockIdx.y, k0 = c * chunk, k1 = k0 + chunk < count ? k0 + chunk : count;
-    const bool in = i < m && j < n;
-    const bool rowsum = tj == 0 && threadIdx.x % 16 == 0 && i < m;
-    const int ic = i < m ? i : m - 1, jc = j < n ? j : n - 1;
+    const bool rowsum = tj == 0 && jl == 0 && i < m;
     double acc = 0.0, accb = 0.0;
-    for (int64_t k = k0; k < k1; ++k) {
-        // (x and y of an LP that is not OPTIMAL may be NaN: selected away,
-        // never multiplied by a zero weight)
-        const bool ok = st[k] == ST_OPTIMAL;
-        const double wy = ok ? g[k] * Y[k * m + ic] : 0.0;
-        acc = __builtin_fma(wy, ok ? X[k * n + jc] : 0.0, acc);
-        accb = accb + wy;
+    for (int64_t kb = k0; kb < k1; kb += KS) {
+        for (int e = threadIdx.x; e < KS * 16; e += blockDim.x) {
+            const int kk = e / 16, r = e % 16;
+            const int64_t k = kb + kk < k1 ? kb + kk : k1 - 1;
+            const bool ok = kb + kk < k1 && st[k] == ST_OPTIMAL;
+            const int ir = ti * 16 + r < m ? ti * 16 + r : m - 1, jr = tj * 16 + r < n ? tj * 16 + r : n - 1;
+            const double yv = Y[k * m + ir], xv = X[k * n + jr], gk = g[k];
+            s_y[kk][r] = ok ? gk * yv : 0.0;
+            s_x[kk][r] = ok ? xv : 0.0;
+        }
+        __syncthreads();
+        const int kn = k1 - kb < KS ? (int)(k1 - kb) : KS;
+        for (int kk = 0; kk < kn; ++kk) {
+            const double wy = s_y[kk][il];
+            acc = __builtin_fma(wy, s_x[kk][jl], acc);
+            accb = accb + wy;
+        }
+        __syncthreads();
     }
-    if (in) part_a[c * (int64_t)m * n + (int64_t)i * n + j] = acc;
+    if (i < m && j < n) part_a[c * (int64_t)m * n + (int64_t)i * n + j] = acc;
     if (rowsum) part_b[c * m + i] = accb;
 }
 // out[e] = sign * (sum over the chunks, in order, of part[c len + e])
