@@ -687,19 +687,22 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
             std::fill(sp.maybe.begin(), sp.maybe.end(), 1);
         }
     }
-    // A uniform batch small enough that every LP gets a workgroup of its own
-    // at once, with a register variant that holds the shape whatever its
-    // number of artificial rows: one launch, LP k in workgroup k.  Binning
-    // would only choose among tiles that give the same bits, and it costs
-    // four launches, about as long as solving such a batch.
+    // A uniform batch small enough that every LP gets a place of its own at
+    // once (a workgroup, or a lane of the lane kernel once the batch is large
+    // enough for it), with a register variant that holds the shape whatever
+    // its number of artificial rows: one launch, LP k in workgroup k (lane
+    // k mod 64 of wave k / 64).  Binning would only choose among tiles that
+    // give the same bits, and it costs four launches, about as long as
+    // solving such a batch.
     sp.direct_v = -1;
     if (uni && any_simplex && h->opt.variant == -1 && h->opt.mode == BLP_MODE_PERSISTENT) {
         const int m = h->plan.m[0], n = h->plan.n[0];
         long barea = -1;
         for (int v = 0; v < nreg; ++v) {
             const RegVariant& rv = h->variants[v];
-            if (rv.max_rows >= m + 2 && rv.max_cols >= n + m + 1 && !rv.type1_only && rv.lps_per_block == 1 &&
-                h->remap[v] == v && K <= h->reg_workers[v]) {
+            const int64_t per = rv.lps_per_block;
+            if (rv.max_rows >= m + 2 && rv.max_cols >= n + m + 1 && !rv.type1_only && h->remap[v] == v &&
+                K <= (int64_t)h->reg_workers[v] * per && (per == 1 || K >= auto_min_count(h, v))) {
                 const long a = (long)rv.max_rows * rv.max_cols;
                 if (barea < 0 || a < barea) {
                     barea = a;
@@ -950,7 +953,8 @@ static blp_error enqueue_direct(blp_handle h, SolvePlan& sp, hipStream_t s) {
     Q.direct_end = 0;
     Q.bin = v;
     HIP_TRY(h, h->mark(v, true, s));
-    HIP_TRY(h, h->variants[v].launch(Q, (int)Q.count, s));
+    const int64_t per = h->variants[v].lps_per_block;
+    HIP_TRY(h, h->variants[v].launch(Q, (int)((Q.count + per - 1) / per), s));
     HIP_TRY(h, h->mark(v, false, s));
     return BLP_SUCCESS;
 }

@@ -158,6 +158,43 @@ def test_small_uniform_batch_runs_as_one_launch():
     assert np.array_equal(_bits(gb["obj"][:1000]), _bits(g["obj"]))
 
 
+def test_uniform_lane_batch_runs_as_one_launch():
+    """A uniform batch of tiny LPs large enough for the lane kernel (one LP
+    per lane) and small enough for all of them to be resident at once runs
+    as one launch of the lane tile that holds the shape for any number of
+    artificial rows (7 x 11 for 5 x 5 LPs), with no binning: strict against
+    the oracle, and the same bits as the binned solve of a larger batch
+    with the same leading LPs."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    K = 20_000
+    hb = lpgen.config(1, range(K))
+    db = blp.DeviceBatch.from_host(hb)
+    s = blp.Solver(profile=True)
+    out = s.solve(db)
+    torch.cuda.synchronize()
+    bins = blp.blp_last_bins(s.h)
+    ms = blp.blp_last_kernel_ms(s.h)
+    s.close()
+    nz = np.nonzero(bins)[0]
+    assert len(nz) == 1 and bins[nz[0]] == K, bins
+    name, rows, cols = blp.variants()[nz[0]]
+    assert name.startswith("l64_") and rows >= 5 + 2 and cols >= 5 + 5 + 1, name
+    assert ms[nz[0]] > 0 and ms[-1] == 0, ms  # no binning
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("status", "iters", "obj"):
+        g[k] = g[k][:K]
+    compare(hb, g, oracle.solve_batch(hb), strict=True, tag="one-launch lane")
+    gg = gpu_solve(hb, graph=True)
+    for k in ("obj", "x", "y"):
+        assert np.array_equal(_bits(gg[k]), _bits(g[k])), k
+    big = lpgen.config(1, range(300_000))
+    gb = gpu_solve(big)
+    assert gb["bins"].sum() == 300_000 and gb["bins"][nz[0]] < 300_000, gb["bins"]
+    assert np.array_equal(_bits(gb["obj"][:K]), _bits(g["obj"]))
+
+
 def test_profile_and_bins():
     import torch
 
