@@ -31,6 +31,7 @@ METRIC = "LPs/sec per size class, batched persistent vs one-LP-per-launch, obj r
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel__type1_m100_n100_K50000.json")
 KERNEL_SOURCES = ["paper_1609_08114_amd/csrc/simplex_reg.hip", "paper_1609_08114_amd/csrc/simplex_blk.hpp",
                   "paper_1609_08114_amd/csrc/simplex_cols.hpp", "paper_1609_08114_amd/csrc/simplex_lane.hpp",
+                  "paper_1609_08114_amd/csrc/simplex_lane.hip",
                   "paper_1609_08114_amd/csrc/simplex_common.hpp", "paper_1609_08114_amd/csrc/blp_kernels.hpp",
                   "paper_1609_08114_amd/csrc/variants.hpp"]
 

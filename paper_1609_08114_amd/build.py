@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libblp.so")
 # for the per-phase breakdown of a solve; never the default
 LIB_TIMERS = os.path.join(HERE, "libblp_timers.so")
 BUILD_TIMERS = os.path.join(HERE, "_build_timers")
-SOURCES = ["simplex_reg.hip", "simplex_gm.hip", "aux_kernels.hip", "blp_runtime.cpp"]
+SOURCES = ["simplex_reg.hip", "simplex_lane.hip", "simplex_gm.hip", "aux_kernels.hip", "blp_runtime.cpp"]
 HEADERS = ["blp_kernels.hpp", "simplex_common.hpp", "simplex_blk.hpp", "simplex_lane.hpp", "simplex_cols.hpp", "variants.hpp",
            "aux_kernels.hpp"]
 

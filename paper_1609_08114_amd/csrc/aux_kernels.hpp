@@ -73,6 +73,13 @@ hipError_t launch_blk_trace(const KParams& P, int grid, hipStream_t s, int tr);
 const void* blk_trace_kernel_ptr(int tr);
 void blk_trace_shape(int* rows, int* cols);
 
+// Lane kernel (simplex_lane.hip): launcher and kernel address of the
+// variant with an R x C tile, NWV waves per workgroup, WPE waves per SIMD.
+template <int R, int C, int NWV, int WPE>
+hipError_t launch_lane(const KParams& P, int grid, hipStream_t s);
+template <int R, int C, int NWV, int WPE>
+const void* kernel_ptr_lane();
+
 // Streaming kernel (simplex_gm.hip).
 // deep: the launch's bin is known not to be empty: for tableaux of up to 512
 // rows, more loads in flight per lane and on-chip columns in the dynamic LDS

@@ -65,6 +65,13 @@ struct DevBuf {
 // Bump allocator over one caller-independent device region (the static
 // scratch array of the allocation-free entry point): hands out 256-byte
 // aligned pieces, never frees.
+// Bin counters of a solve, in ints: bin_len, bin_fill and bin_off (nbins
+// each), the work-list heads from heads_at(nbins) on (kHeadStride apart,
+// each on a cache line of its own), then kBinStripes striped copies of the
+// bin counts.  The buffer is 256-byte aligned.
+static size_t heads_at(int nbins) { return ((size_t)3 * nbins + kHeadStride - 1) / kHeadStride * kHeadStride; }
+static size_t counter_ints(int nbins) { return heads_at(nbins) + ((size_t)kHeadStride + kBinStripes) * nbins; }
+
 struct Arena {
     char* base = nullptr;
     size_t cap = 0, used = 0;
@@ -120,7 +127,7 @@ struct blp_handle_s {
     int direct_v = -1;  // the last solve's one-launch variant (no binning), or -1
     // device buffers
     DevBuf meta;     // m, n, kind (int32) + a_off, row_off, col_off (int64) for non-uniform batches
-    DevBuf counters; // bin_count, bin_fill, bin_head, bin_off (4 x nbins int32), striped bin counters
+    DevBuf counters; // bin counters of the last solve (layout: counter_ints)
     DevBuf binid, list;
     DevBuf olist;  // non-uniform batches: the work lists in largest-first order (what the kernels pop)
     DevBuf ws;       // streaming-kernel workspace
@@ -633,12 +640,11 @@ static blp_error prepare(blp_handle h, const blp_batch* B, const blp_outputs* ou
     P.timers = h->timers;
 #endif
     const int nreg = h->nreg, nbins = nreg + 2;
-    // bin_count, bin_fill, bin_head, bin_off, then the striped bin counters
-    BUF_TRY(h, arena, h->counters, sizeof(int32_t) * (4 + (size_t)kBinStripes) * nbins, sp.counters);
+    BUF_TRY(h, arena, h->counters, sizeof(int32_t) * counter_ints(nbins), sp.counters);
     int32_t* bin_count = sp.counters;
     P.bin_len = bin_count;
-    P.bin_head = bin_count + 2 * nbins;
-    P.bin_off = bin_count + 3 * nbins;
+    P.bin_off = bin_count + 2 * nbins;
+    P.bin_head = bin_count + heads_at(nbins);
     if (h->opt.profile) HIP_TRY(h, h->ensure_events(nbins + 1));
 
     sp.uni = uni;
@@ -768,8 +774,8 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     int32_t* bin_fill = bin_count + nbins;
     HIP_TRY(h, h->mark(nbins, true, s));
     // zero the counters and the striped bin counters (bin_off is rewritten)
-    int32_t* stripes = bin_count + 4 * nbins;
-    HIP_TRY(h, launch_reset(bin_count, (4 + kBinStripes) * nbins, s));
+    int32_t* stripes = bin_count + heads_at(nbins) + kHeadStride * nbins;
+    HIP_TRY(h, launch_reset(bin_count, (int)counter_ints(nbins), s));
     HIP_TRY(h, launch_classify(sp.P, variant_table(h, sp.P.count), sp.binid, stripes, s));
     HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));
     HIP_TRY(h, launch_scatter(sp.P.count, nbins, sp.binid, sp.P.bin_off, bin_fill, sp.list, s));
@@ -1012,7 +1018,7 @@ static blp_error solve_limited(blp_handle h, const blp_batch* B, const blp_outpu
     const size_t out_bytes = (own_st ? 4 * (size_t)K : 0) + (own_it ? 4 * (size_t)K : 0) +
                              (own_ob ? 8 * (size_t)K : 0) + (own_x ? 8 * (size_t)std::max<int64_t>(1, tot_n) : 0) +
                              (own_y ? 8 * (size_t)std::max<int64_t>(1, tot_m) : 0);
-    const size_t counters = sizeof(int32_t) * (4 + (size_t)kBinStripes) * (h->nreg + 2);
+    const size_t counters = sizeof(int32_t) * counter_ints(h->nreg + 2);
     const size_t slot = any_simplex ? sizeof(double) * (size_t)max_slot : 0;
     const size_t per_lp = uni ? 8 : 48;
     const size_t fixed = out_bytes + counters + slot;

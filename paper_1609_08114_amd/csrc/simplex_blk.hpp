@@ -244,7 +244,7 @@ simplex_blk_kernel(KParams P) {
                 int64_t q;
                 if (SH) {
                     if (s_cur >= s_end) {
-                        const int64_t c0 = (int64_t)atomicAdd(P.bin_head + P.bin, 1) * P.chunk;
+                        const int64_t c0 = (int64_t)atomicAdd(bin_head_of(P), 1) * P.chunk;
                         s_cur = c0 < len ? c0 : len;
                         s_end = c0 + P.chunk < len ? c0 + P.chunk : len;
                     }
@@ -257,7 +257,7 @@ simplex_blk_kernel(KParams P) {
             s_k = kk;
             s_bad = 0;
             if (!SH && !P.direct) {  // reserve the next position (after the LDS write: no wait for it)
-                pf_q = kk >= 0 ? atomicAdd(P.bin_head + P.bin, 1) : (int)len;
+                pf_q = kk >= 0 ? atomicAdd(bin_head_of(P), 1) : (int)len;
                 pf_k = -2;
             }
         }

@@ -108,7 +108,7 @@ simplex_cols_kernel(KParams P) {
             s_k = kk;
             s_bad = 0;
             if (!P.direct) {
-                pf_q = kk >= 0 ? atomicAdd(P.bin_head + P.bin, 1) : (int)len;
+                pf_q = kk >= 0 ? atomicAdd(bin_head_of(P), 1) : (int)len;
                 pf_k = -2;
             }
         }

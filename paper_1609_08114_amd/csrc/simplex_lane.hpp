@@ -51,7 +51,7 @@ simplex_lane_kernel(KParams P) {
         } else {
             int v = 0;
             if (lane == 0) {
-                int* head = P.bin_head + P.bin;
+                int* head = bin_head_of(P);
                 // an exhausted (or empty) list: leave without an atomic
                 v = first && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len
                         ? (int)len

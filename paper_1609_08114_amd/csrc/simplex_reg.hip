@@ -23,10 +23,10 @@
 // ratio test -> owners of the pivot row publish it -> barrier -> divide by
 // the pivot element (Step 3's NewPivotRow) -> barrier -> register update and
 // mirrors -> barrier.
+#include "aux_kernels.hpp"
 #include "blp_kernels.hpp"
 #include "simplex_blk.hpp"
 #include "simplex_common.hpp"
-#include "simplex_lane.hpp"
 #include "simplex_cols.hpp"
 #include "variants.hpp"
 
@@ -414,16 +414,6 @@ static hipError_t launch_cols(const KParams& P, int grid, hipStream_t s) {
 template <int NW, int GCW, int RB, int CB, int WPE>
 static const void* kernel_ptr_cols() {
     return reinterpret_cast<const void*>(&simplex_cols_kernel<NW, GCW, RB, CB, WPE>);
-}
-
-template <int R, int C, int NWV, int WPE>
-static hipError_t launch_lane(const KParams& P, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((simplex_lane_kernel<R, C, NWV, WPE>), dim3(grid), dim3(NWV * 64), 0, s, P);
-    return hipGetLastError();
-}
-template <int R, int C, int NWV, int WPE>
-static const void* kernel_ptr_lane() {
-    return reinterpret_cast<const void*>(&simplex_lane_kernel<R, C, NWV, WPE>);
 }
 
 // Pivot trace of the 112 x 112 block tile (the kernel of the 100 x 100

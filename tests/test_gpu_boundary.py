@@ -44,7 +44,10 @@ def test_mem_limit_chunks_identical():
         # streaming slot of the largest LP, then room for 37 LPs
         m, n = hb.m.astype(np.int64), hb.n.astype(np.int64)
         slot = int((((m + 2 + 15) // 16) * 16 * (n + m + 1) * 8)[hb.kind == 0].max())
-        counters = 4 * (4 + 64) * (len(blp.variants()) + 2)
+        # bin counters: lengths, fill counts and offsets, the work-list heads
+        # one 128-byte line apart, then 64 striped copies of the counts
+        nbins = len(blp.variants()) + 2
+        counters = 4 * (-(-3 * nbins // 32) * 32 + (32 + 64) * nbins)
         limit = counters + slot + 37 * per_lp
         s = blp.Solver(mem_limit=limit)
         try:
