@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable v
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += blockDim.x)
-        if (hist[b]) atomicAdd(stripes + b * kBinStripes + (blockIdx.x % kBinStripes), hist[b]);
+        if (hist[b]) atomicAdd(stripes + (blockIdx.x % kBinStripes) * kStripeStride + b, hist[b]);
 }
 
 // Bin sizes (the kBinStripes copies summed) and their exclusive prefix: wave
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) bin_offsets_kernel(const int32_t* stripes
 #pragma unroll
     for (int u = 0; u < (kMaxVariants + 2 + 3) / 4; ++u) {
         const int b = wave + 4 * u;
-        v[u] = b < nbins ? stripes[b * kBinStripes + lane] : 0;
+        v[u] = b < nbins ? stripes[lane * kStripeStride + b] : 0;
     }
 #pragma unroll
     for (int u = 0; u < (kMaxVariants + 2 + 3) / 4; ++u) {

@@ -28,11 +28,14 @@ struct VariantTable {
 
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);
 // classify adds its blocks' bin histograms into kBinStripes copies of the
-// bin counters (stripes[bin * kBinStripes + stripe], zeroed beforehand);
-// bin_offsets sums the copies into bin_count and writes the exclusive prefix
-// to bin_off.
+// bin counters, one 128-byte line per copy (stripes[stripe * kStripeStride +
+// bin], zeroed beforehand), so that the blocks' atomics spread over
+// kBinStripes lines; bin_offsets sums the copies into bin_count and writes
+// the exclusive prefix to bin_off.
 constexpr int kClassifyMaxBlocks = 2048;
 constexpr int kBinStripes = 64;
+constexpr int kStripeStride = 32;
+static_assert(kMaxVariants + 2 <= kStripeStride, "every bin of a stripe on its line");
 int classify_blocks(int64_t count);
 hipError_t launch_classify(const KParams& P, const VariantTable& vt, int32_t* binid, int32_t* stripes,
                            hipStream_t s);

@@ -68,9 +68,10 @@ struct DevBuf {
 // Bin counters of a solve, in ints: bin_len, bin_fill and bin_off (nbins
 // each), the work-list heads from heads_at(nbins) on (kHeadStride apart,
 // each on a cache line of its own), then kBinStripes striped copies of the
-// bin counts.  The buffer is 256-byte aligned.
+// bin counts (kStripeStride apart).  The buffer is 256-byte aligned.
 static size_t heads_at(int nbins) { return ((size_t)3 * nbins + kHeadStride - 1) / kHeadStride * kHeadStride; }
-static size_t counter_ints(int nbins) { return heads_at(nbins) + ((size_t)kHeadStride + kBinStripes) * nbins; }
+static size_t stripes_at(int nbins) { return heads_at(nbins) + (size_t)kHeadStride * nbins; }
+static size_t counter_ints(int nbins) { return stripes_at(nbins) + (size_t)kBinStripes * kStripeStride; }
 
 struct Arena {
     char* base = nullptr;
@@ -774,7 +775,7 @@ static blp_error enqueue_binning(blp_handle h, SolvePlan& sp, hipStream_t s) {
     int32_t* bin_fill = bin_count + nbins;
     HIP_TRY(h, h->mark(nbins, true, s));
     // zero the counters and the striped bin counters (bin_off is rewritten)
-    int32_t* stripes = bin_count + heads_at(nbins) + kHeadStride * nbins;
+    int32_t* stripes = bin_count + stripes_at(nbins);
     HIP_TRY(h, launch_reset(bin_count, (int)counter_ints(nbins), s));
     HIP_TRY(h, launch_classify(sp.P, variant_table(h, sp.P.count), sp.binid, stripes, s));
     HIP_TRY(h, launch_bin_offsets(stripes, bin_count, const_cast<int32_t*>(sp.P.bin_off), nbins, s));

@@ -45,9 +45,10 @@ def test_mem_limit_chunks_identical():
         m, n = hb.m.astype(np.int64), hb.n.astype(np.int64)
         slot = int((((m + 2 + 15) // 16) * 16 * (n + m + 1) * 8)[hb.kind == 0].max())
         # bin counters: lengths, fill counts and offsets, the work-list heads
-        # one 128-byte line apart, then 64 striped copies of the counts
+        # one 128-byte line apart, then 64 striped copies of the counts, one
+        # 128-byte line each
         nbins = len(blp.variants()) + 2
-        counters = 4 * (-(-3 * nbins // 32) * 32 + (32 + 64) * nbins)
+        counters = 4 * (-(-3 * nbins // 32) * 32 + 32 * nbins + 64 * 32)
         limit = counters + slot + 37 * per_lp
         s = blp.Solver(mem_limit=limit)
         try:
