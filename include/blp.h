@@ -241,11 +241,16 @@ blp_error blp_solve_batch_host(blp_handle h, const blp_batch* batch, const blp_o
  * up to the limits of blp_solve_batch (m <= 2046, n + m + 1 <= 4096, else
  * BLP_ERR_TOO_LARGE), are solved from scratch for every objective by the
  * smallest register-tile variant that holds them, else the streaming kernel.
- * A handle whose options force a register-tile variant (variant >= 0) runs
- * the cold solves with that variant, and fails with BLP_ERR_TOO_LARGE if it
- * cannot hold them.  Reads b, sense and the first 65 objectives back
- * to the host once (synchronising the stream); the solve itself is ordered
- * on the stream.
+ * The route (warm starts, a register variant, or the streaming kernel) is
+ * chosen on the device from b, sense and the first 65 objectives, so the
+ * call is ordered on the stream and reads nothing back; it allocates its
+ * work buffers on first use and when count grows (a call whose count and
+ * shape do not exceed an earlier one's allocates nothing, and can be
+ * captured in a HIP graph).  A handle whose options force a register-tile
+ * variant (variant >= 0) runs the cold solves with that variant, and fails
+ * with BLP_ERR_TOO_LARGE if it cannot hold them; to know that, it reads b,
+ * sense and the first 65 objectives back to the host once (synchronising
+ * the stream).
  * The handle keeps no results of this call (blp_backward and
  * blp_get_solution refer to the last blp_solve_batch). */
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,

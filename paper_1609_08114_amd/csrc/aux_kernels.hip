@@ -440,6 +440,67 @@ __global__ void backward_hyperbox_kernel(KParams P, const double* g, double* dc,
 }
 
 // ------------------------------------------------------------------ launchers
+__global__ void __launch_bounds__(256) shared_route_kernel(int m, int n, int64_t count, const double* b,
+                                                            const int8_t* sense, const double* C, SharedRoute rt,
+                                                            int32_t* route_len) {
+    __shared__ int s_nart[4], s_close[4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int na = 0;
+    for (int i = t; i < m; i += 256) {
+        const double bi = b[i];
+        na += (sense[i] ? -bi : bi) < 0.0;
+    }
+    for (int o = 32; o >= 1; o >>= 1) na += __shfl_xor(na, o);
+    const int64_t ns = count < 65 ? count : 65;
+    int close = 0;
+    for (int64_t k = 1 + wave; k < ns; k += 4) {
+        const double* u = C + k * n;
+        const double* v = C + (k - 1) * n;
+        double dot = 0.0, aa = 0.0, bb = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            dot += u[j] * v[j];
+            aa += u[j] * u[j];
+            bb += v[j] * v[j];
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            dot += __shfl_xor(dot, o);
+            aa += __shfl_xor(aa, o);
+            bb += __shfl_xor(bb, o);
+        }
+        close += dot > 0.9 * sqrt(aa * bb);  // false for non-finite objectives
+    }
+    if (lane == 0) {
+        s_nart[wave] = na;
+        s_close[wave] = close;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const int nart = s_nart[0] + s_nart[1] + s_nart[2] + s_nart[3];
+        const int64_t cl = s_close[0] + s_close[1] + s_close[2] + s_close[3];
+        const int r = shared_route_of(rt, m, n, nart, ns > 1 && 2 * cl >= ns - 1);
+        for (int i = 0; i < rt.nreg + 2; ++i) route_len[i] = i == r ? (int)count : 0;
+    }
+}
+
+__global__ void iota_kernel(int32_t* list, int64_t count) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x)
+        list[q] = (int32_t)q;
+}
+
+hipError_t launch_shared_route(int m, int n, int64_t count, const double* b, const int8_t* sense, const double* C,
+                               const SharedRoute& rt, int32_t* route_len, hipStream_t s) {
+    hipLaunchKernelGGL(shared_route_kernel, dim3(1), dim3(256), 0, s, m, n, count, b, sense, C, rt, route_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* list, int64_t count, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)blocks), dim3(256), 0, s, list, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s) {
     hipLaunchKernelGGL(reset_bins_kernel, dim3(1), dim3(256), 0, s, counters, n);
     return hipGetLastError();

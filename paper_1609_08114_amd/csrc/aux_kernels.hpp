@@ -64,6 +64,47 @@ hipError_t launch_backward_shared(int64_t count, int m, int n, const int32_t* st
 hipError_t launch_backward_box_shared(const KParams& P, int n, const double* g, double* part, double* dl, double* du,
                                       hipStream_t s);
 
+// Route of a shared-constraint solve (one A, b, sense; many objectives),
+// decided on the device so that the call reads nothing back: bin nreg + 1 is
+// the warm-started shared kernel, bins 0..nreg-1 the register variants
+// (every objective solved cold), bin nreg the streaming kernel.
+struct SharedRoute {
+    int nreg;
+    int rows[kMaxVariants], cols[kMaxVariants], type1[kMaxVariants];
+    int tile_rows, tile_cols;  // tableau of the warm-started kernel
+};
+// The route for n_art artificial rows; warm_dirs: consecutive objectives
+// point in close directions.  Warm starts when the shared tile holds the
+// tableau; otherwise the register variant of the shared tile's shape, else
+// the one of smallest area (the first of equal areas), that holds it; else
+// the streaming kernel.  Variants for LPs without artificial rows only
+// (type1) are never taken.
+__host__ __device__ inline int shared_route_of(const SharedRoute& rt, int m, int n, int nart, bool warm_dirs) {
+    if (warm_dirs && m + 2 <= rt.tile_rows && n + nart + 1 <= rt.tile_cols) return rt.nreg + 1;
+    for (int i = 0; i < rt.nreg; ++i)
+        if (rt.rows[i] == rt.tile_rows && rt.cols[i] == rt.tile_cols && !rt.type1[i] && m + 2 <= rt.rows[i] &&
+            n + nart + 1 <= rt.cols[i])
+            return i;
+    int v = rt.nreg;
+    long best = -1;
+    for (int i = 0; i < rt.nreg; ++i)
+        if (rt.rows[i] >= m + 2 && rt.cols[i] >= n + nart + 1 && !rt.type1[i]) {
+            const long a = (long)rt.rows[i] * rt.cols[i];
+            if (best < 0 || a < best) {
+                best = a;
+                v = i;
+            }
+        }
+    return v;
+}
+// One workgroup: n_art from b and sense, the close pairs among the first
+// 65 objectives (cosine > 0.9, warm when at least half are), then
+// route_len[r] = count for the chosen route r and 0 for the others.
+hipError_t launch_shared_route(int m, int n, int64_t count, const double* b, const int8_t* sense, const double* C,
+                               const SharedRoute& rt, int32_t* route_len, hipStream_t s);
+// list[q] = q for q < count
+hipError_t launch_iota(int32_t* list, int64_t count, hipStream_t s);
+
 // Shared-constraint kernel (simplex_reg.hip): tableau shape and launcher.
 hipError_t launch_shared(const KParams& P, int grid, hipStream_t s);
 const void* shared_kernel_ptr();

@@ -182,7 +182,10 @@ struct blp_handle_s {
         return hipSuccess;
     }
     DevBuf tune;  // autotuner scratch (sample list + counters)
-    DevBuf shared_ctr;  // queue head of blp_solve_shared
+    DevBuf shared_ctr;  // blp_solve_shared: route lengths, zero offsets and queue heads
+    DevBuf shared_list; // blp_solve_shared: the identity work list (shared_list_n entries filled)
+    int64_t shared_list_n = 0;
+    DevBuf shared_ws;   // blp_solve_shared: streaming workspace of the cold route
     // host-resident pipeline: two child handles (own buffers), two streams,
     // two device input/output sets
     blp_handle_s* child[2] = {nullptr, nullptr};
@@ -434,6 +437,8 @@ void blp_destroy(blp_handle h) {
         h->pin_out[i].release();
     }
     h->shared_ctr.release();
+    h->shared_list.release();
+    h->shared_ws.release();
     h->bwd_part.release();
     delete h;
 }
@@ -1282,6 +1287,58 @@ blp_error blp_backward_shared(blp_handle h, int32_t m, int32_t n, int64_t count,
 }
 
 // ------------------------------------------------ host-resident pipeline
+// The warm-started shared kernel: persistent workgroups taking chunks of
+// consecutive objectives (the warm starts run along a chunk), at least 8 per
+// chunk and about four chunks per workgroup for balance.
+static blp_error launch_shared_warm(blp_handle h, KParams& P, hipStream_t s) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, shared_kernel_ptr(), shared_threads(), 0) != hipSuccess ||
+        occ < 1)
+        occ = 1;
+    const int64_t workers = (int64_t)occ * h->cu_count;
+    P.chunk = std::max<int64_t>(8, (P.count + 4 * workers - 1) / (4 * workers));
+    const int grid = (int)std::min<int64_t>(workers, (P.count + P.chunk - 1) / P.chunk);
+    HIP_TRY(h, launch_shared(P, grid, s));
+    return BLP_SUCCESS;
+}
+
+// blp_solve_shared on a handle that forces a register variant: the route is
+// decided on the host (b, sense and the first 65 objectives read back), so
+// that a variant that cannot hold the constraints fails the call.
+static blp_error solve_shared_forced(blp_handle h, KParams& P, int rows, int cols, hipStream_t s) {
+    const int m = P.um, n = P.un;
+    const int64_t count = P.count;
+    std::vector<double> hb(m);
+    std::vector<int8_t> hs(m);
+    const int64_t ns = std::min<int64_t>(count, 65);
+    std::vector<double> hc((size_t)std::max<int64_t>(ns, 1) * n);
+    HIP_TRY(h, hipMemcpyAsync(hb.data(), P.b, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(hs.data(), P.sense, (size_t)m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(hc.data(), P.c, sizeof(double) * ns * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    int close = 0;
+    for (int64_t k = 1; k < ns; ++k) {
+        double dot = 0.0, aa = 0.0, bb = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double u = hc[(size_t)k * n + j], v = hc[(size_t)(k - 1) * n + j];
+            dot += u * v;
+            aa += u * u;
+            bb += v * v;
+        }
+        close += dot > 0.9 * std::sqrt(aa * bb);
+    }
+    int nart = 0;
+    for (int i = 0; i < m; ++i) nart += (hs[i] ? -hb[i] : hb[i]) < 0.0;
+    if (ns > 1 && 2 * close >= ns - 1 && m + 2 <= rows && n + nart + 1 <= cols) return launch_shared_warm(h, P, s);
+    const int v = h->opt.variant;
+    if (h->variants[v].max_rows < m + 2 || h->variants[v].max_cols < n + nart + 1 ||
+        (h->variants[v].type1_only && (nart > 0 || h->opt.pivot_rule != BLP_RULE_LPC)))
+        return fail(h, BLP_ERR_TOO_LARGE, "variant %s cannot hold the shared constraints", h->variants[v].name);
+    P.shared_in = 1;
+    HIP_TRY(h, h->variants[v].launch(P, reg_grid(h, v, count), s));
+    return BLP_SUCCESS;
+}
+
 blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, const double* b,
                            const int8_t* sense, int64_t count, const double* C, const blp_outputs* out,
                            void* stream) {
@@ -1298,34 +1355,8 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
     shared_shape(&rows, &cols);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(h, hipSetDevice(h->opt.device));
-    HIP_TRY(h, begin_call(h, s));
-    // the tableau width depends on how many rows need an artificial variable;
-    // the first objectives tell whether consecutive directions are close
-    // enough for warm starts
-    std::vector<double> hb(m);
-    std::vector<int8_t> hs(m);
-    const int64_t ns = std::min<int64_t>(count, 65);
-    std::vector<double> hc((size_t)std::max<int64_t>(ns, 1) * n);
-    HIP_TRY(h, hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipMemcpyAsync(hs.data(), sense, (size_t)m, hipMemcpyDeviceToHost, s));
-    if (ns > 0) HIP_TRY(h, hipMemcpyAsync(hc.data(), C, sizeof(double) * ns * n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipStreamSynchronize(s));
-    int close = 0;
-    for (int64_t k = 1; k < ns; ++k) {
-        double dot = 0.0, aa = 0.0, bb = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double u = hc[(size_t)k * n + j], v = hc[(size_t)(k - 1) * n + j];
-            dot += u * v;
-            aa += u * u;
-            bb += v * v;
-        }
-        close += dot > 0.9 * std::sqrt(aa * bb);
-    }
-    int nart = 0;
-    for (int i = 0; i < m; ++i) nart += (hs[i] ? -hb[i] : hb[i]) < 0.0;
-    // warm starts need the shared tile; larger sets take the cold route
-    const bool warm = ns > 1 && 2 * close >= ns - 1 && m + 2 <= rows && n + nart + 1 <= cols;
     if (count == 0) return BLP_SUCCESS;
+    HIP_TRY(h, begin_call(h, s));
     KParams P{};
     P.count = count;
     P.uniform = 1;
@@ -1352,84 +1383,87 @@ blp_error blp_solve_shared(blp_handle h, int32_t m, int32_t n, const double* A, 
 #ifdef BLP_PHASE_TIMERS
     P.timers = h->timers;
 #endif
-    HIP_TRY(h, h->shared_ctr.reserve(sizeof(int32_t) * 64));
-    P.bin_head = h->shared_ctr.as<int32_t>();
+    const int nreg = h->nreg, nb = nreg + 2;
+    // route lengths (nb), zero list offsets (nb), then one queue head per
+    // route, each on a cache line of its own
+    const size_t heads = ((size_t)2 * nb + kHeadStride - 1) / kHeadStride * kHeadStride;
+    const size_t ints = heads + (size_t)kHeadStride * nb;
+    HIP_TRY(h, h->shared_ctr.reserve(sizeof(int32_t) * ints));
+    int32_t* rb = h->shared_ctr.as<int32_t>();
+    HIP_TRY(h, launch_reset(rb, (int)ints, s));
+    P.bin_head = rb + heads;
     P.bin = 0;
-    if (!warm) {
-        // unrelated directions, or constraints beyond the shared tile: every
-        // objective is a cold solve, every LP reading the one constraint set.
-        // They all have the same tableau shape (the artificial rows come from
-        // b and sense), so one kernel takes them all: the forced variant, else
-        // the register variant of smallest area that holds the shape (the
-        // shared tile's shape first), else the streaming kernel.
-        int v = -1;
-        if (h->opt.variant >= 0) {
-            v = h->opt.variant;
-            if (h->variants[v].max_rows < m + 2 || h->variants[v].max_cols < n + nart + 1 ||
-                (h->variants[v].type1_only && (nart > 0 || h->opt.pivot_rule != BLP_RULE_LPC)))
-                return fail(h, BLP_ERR_TOO_LARGE, "variant %s cannot hold the shared constraints",
-                            h->variants[v].name);
-        }
-        for (int i = 0; i < h->nreg && v < 0; ++i)
-            if (h->variants[i].max_rows == rows && h->variants[i].max_cols == cols && !h->variants[i].type1_only &&
-                m + 2 <= rows && n + nart + 1 <= cols)
-                v = i;
-        long barea = -1;
-        for (int i = 0; i < h->nreg && h->opt.variant < 0 && (v < 0 || barea >= 0); ++i) {
-            const RegVariant& rv = h->variants[i];
-            if (rv.max_rows >= m + 2 && rv.max_cols >= n + nart + 1 && !rv.type1_only) {
-                const long a = (long)rv.max_rows * rv.max_cols;
-                if (barea < 0 || a < barea) {
-                    barea = a;
-                    v = i;
-                }
-            }
-        }
-        if (v >= 0) {
-            P.shared_in = 1;
-            HIP_TRY(h, launch_reset(P.bin_head, 1, s));
-            HIP_TRY(h, h->variants[v].launch(P, reg_grid(h, v, count), s));
-            HIP_TRY(h, end_call(h, s));
-            return BLP_SUCCESS;
-        }
-        // the streaming kernel, its workspace and LDS planned as for a
-        // uniform batch of this shape
-        const int32_t km = m, kn = n, kk = 0;
-        blp_batch B{};
-        B.count = count;
-        B.uniform = 1;
-        B.m = &km;
-        B.n = &kn;
-        B.kind = &kk;
-        B.A = A;
-        B.b = b;
-        B.sense = sense;
-        B.c = C;
-        SolvePlan sp;
-        blp_error pe = prepare(h, &B, out, s, sp);
-        if (pe != BLP_SUCCESS) return pe;
-        KParams Q = sp.P;
-        Q.shared_in = 1;
-        Q.list = nullptr;
-        Q.direct = 0;
-        Q.bin = 0;
-        Q.bin_head = P.bin_head;
-        HIP_TRY(h, launch_reset(Q.bin_head, 1, s));
-        HIP_TRY(h, launch_gm(Q, (int)std::min<int64_t>(sp.gm_workers, count), sp.gm_lds, s, sp.gm_deep));
+    if (h->opt.variant >= 0) {
+        blp_error e = solve_shared_forced(h, P, rows, cols, s);
+        if (e != BLP_SUCCESS) return e;
         HIP_TRY(h, end_call(h, s));
         return BLP_SUCCESS;
     }
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, shared_kernel_ptr(), shared_threads(), 0) != hipSuccess ||
-        occ < 1)
-        occ = 1;
-    const int64_t workers = (int64_t)occ * h->cu_count;
-    // chunks of consecutive objectives (the warm starts run along a chunk):
-    // at least 8 per chunk, about four chunks per workgroup for balance
-    P.chunk = std::max<int64_t>(8, (count + 4 * workers - 1) / (4 * workers));
-    const int grid = (int)std::min<int64_t>(workers, (count + P.chunk - 1) / P.chunk);
-    HIP_TRY(h, launch_reset(P.bin_head, 1, s));
-    HIP_TRY(h, launch_shared(P, grid, s));
+    // The route (warm starts, one register variant, or the streaming kernel)
+    // depends on b, sense and the first objectives, which are device data:
+    // a one-workgroup kernel picks it and writes the work length of every
+    // route (count for the chosen one, 0 for the others), and every route
+    // that some number of artificial rows could select is launched over the
+    // identity list; the others leave at their first look at the list.
+    SharedRoute rt{};
+    rt.nreg = nreg;
+    for (int v = 0; v < nreg && v < kMaxVariants; ++v) {
+        rt.rows[v] = h->variants[v].max_rows;
+        rt.cols[v] = h->variants[v].max_cols;
+        rt.type1[v] = h->variants[v].type1_only;
+    }
+    rt.tile_rows = rows;
+    rt.tile_cols = cols;
+    std::vector<char> cand(nb, 0);
+    for (int na = 0; na <= m; ++na) {
+        cand[shared_route_of(rt, m, n, na, false)] = 1;
+        if (count > 1) cand[shared_route_of(rt, m, n, na, true)] = 1;
+    }
+    if (count > h->shared_list_n) {
+        h->shared_list_n = 0;
+        HIP_TRY(h, h->shared_list.reserve(sizeof(int32_t) * (size_t)count));
+        HIP_TRY(h, launch_iota(h->shared_list.as<int32_t>(), count, s));
+        h->shared_list_n = count;
+    }
+    HIP_TRY(h, launch_shared_route(m, n, count, b, sense, C, rt, rb, s));
+    P.list = h->shared_list.as<int32_t>();
+    P.bin_len = rb;
+    P.bin_off = rb + nb;
+    if (cand[nreg + 1]) {
+        KParams Q = P;
+        Q.bin = nreg + 1;
+        blp_error e = launch_shared_warm(h, Q, s);
+        if (e != BLP_SUCCESS) return e;
+    }
+    for (int v = 0; v < nreg; ++v) {
+        if (!cand[v]) continue;
+        KParams Q = P;
+        Q.bin = v;
+        Q.shared_in = 1;
+        HIP_TRY(h, h->variants[v].launch(Q, reg_grid(h, v, count), s));
+    }
+    if (cand[nreg]) {
+        // the streaming kernel with on-chip columns (nothing else runs beside
+        // it), one workspace slot per workgroup for the widest tableau the
+        // constraints can give (every row artificial)
+        KParams Q = P;
+        Q.bin = nreg;
+        Q.shared_in = 1;
+        const int ld = ((m + 2 + 15) / 16) * 16, gcols = n + m + 1;
+        const bool deep = true;
+        int occ = 1;
+        size_t lds = 0;
+        gm_lds_plan(h, ld, gcols, deep, false, &lds, &Q.ws_lds, &occ);
+        if (h->opt.workers_per_cu > 0) occ = std::min(occ, (int)h->opt.workers_per_cu);
+        const int64_t workers = std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * h->cu_count, count));
+        const size_t slot = (size_t)ld * gcols;
+        HIP_TRY(h, h->shared_ws.reserve(sizeof(double) * slot * (size_t)workers));
+        Q.ws = h->shared_ws.as<double>();
+        Q.ws_slot = (int64_t)slot;
+        Q.ws_ld = ld;
+        Q.ws_cols = gcols;
+        HIP_TRY(h, launch_gm(Q, (int)workers, lds, s, deep));
+    }
     HIP_TRY(h, end_call(h, s));
     return BLP_SUCCESS;
 }

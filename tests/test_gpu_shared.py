@@ -301,3 +301,64 @@ def test_shared_adjoint():
         assert o2["status"][:len(lps)].cpu().numpy().max() == 0
     finally:
         s2.close()
+
+
+def test_shared_solve_is_stream_ordered():
+    """The route of a shared-constraint solve is chosen on the device and
+    nothing is read back, so the call can be captured in a graph once an
+    eager call has sized its buffers: every replay (with other work on the
+    GPU between them) gives the eager call's bits, for a swept circle (warm
+    starts), random directions (cold, register tile) and a two-phase 200 x
+    200 set (cold, streaming kernel)."""
+    import torch
+
+    import paper_1609_08114_amd as blp
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(8)
+    lp = lpgen.config(2, [11]).lp(0)
+    u, v = rng.normal(size=(2, 100))
+    t = np.linspace(0.0, 2.0 * np.pi, 600, endpoint=False)
+    sweep = np.cos(t)[:, None] * u + np.sin(t)[:, None] * v
+    h3 = lpgen.config(3, range(0, 1))
+    m3, n3 = int(h3.m[0]), int(h3.n[0])
+    cases = [("sweep", lp["A"], lp["b"], lp["sense"], sweep),
+             ("random", lp["A"], lp["b"], lp["sense"], rng.normal(size=(300, 100))),
+             ("streaming", h3.A[:m3 * n3].reshape(m3, n3), h3.b[:m3], h3.sense[:m3],
+              rng.uniform(1.0, 10.0, size=(24, n3)))]
+    for tag, A, b, sense, C in cases:
+        print(f"[shared] graph capture {tag}", flush=True)
+        Ad = torch.from_numpy(np.ascontiguousarray(A, np.float64).ravel()).to(dev)
+        bd = torch.from_numpy(np.ascontiguousarray(b, np.float64)).to(dev)
+        sd = torch.from_numpy(np.ascontiguousarray(sense, np.int8)).to(dev)
+        Cd = torch.from_numpy(np.ascontiguousarray(C, np.float64)).to(dev)
+        s = blp.Solver()
+        st = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(st):
+                ref = {k: v.clone() for k, v in s.solve_shared(Ad, bd, sd, Cd).items()}
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=st):
+                out = s.solve_shared(Ad, bd, sd, Cd)
+            torch.cuda.synchronize()
+            for rep in range(3):
+                for k in out:
+                    out[k].fill_(-7)
+                noise = torch.randn(1 << 16, device=dev).sum()
+                g.replay()
+                torch.cuda.synchronize()
+                for k in ("status", "iters", "obj", "x", "y"):
+                    assert torch.equal(out[k].view(torch.int32) if out[k].dtype == torch.float64 else out[k],
+                                       ref[k].view(torch.int32) if ref[k].dtype == torch.float64 else ref[k]), \
+                        (tag, rep, k)
+                del noise
+            del g
+        finally:
+            s.close()
+        o = _oracle(A, b, sense, C)
+        K = C.shape[0]
+        st_ = ref["status"][:K].cpu().numpy()
+        assert np.array_equal(st_, o["status"]), tag
+        ok = o["status"] == oracle.OPTIMAL
+        obj = ref["obj"][:K].cpu().numpy()
+        assert (np.abs(obj[ok] - o["obj"][ok]) <= REL * np.maximum(1.0, np.abs(o["obj"][ok]))).all(), tag
