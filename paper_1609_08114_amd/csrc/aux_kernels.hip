@@ -390,7 +390,11 @@ __global__ void __launch_bounds__(256) box_shared_final_kernel(const double* par
 // Adjoint for simplex LPs: dc = g x*, db = g y*, dA = -g y* x*^T.  One
 // workgroup per LP; LPs not OPTIMAL get zeros.
 __global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const double* g, double* dc, double* db,
-                                                               double* dA) {
+                                                               double* dA, int stage) {
+    // x of the LP, then -(g y) of the LP (when the `stage` doubles of LDS
+    // hold them; else read in place): each dA element is one product of two
+    // such values, written in element order (coalesced)
+    extern __shared__ double s_xy[];
     for (int64_t k = blockIdx.x; k < P.count; k += gridDim.x) {
         if (lp_kind(P, k) != 0) continue;
         const LpRef L = lp_ref(P, k);
@@ -403,13 +407,24 @@ __global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const 
         if (db)
             for (int i = threadIdx.x; i < L.m; i += blockDim.x) db[L.row_off + i] = ok ? gk * y[i] : 0.0;
         if (dA && L.n > 0) {
+            const bool staged = L.n + L.m <= stage;
+            double* sx = s_xy;
+            double* sy = s_xy + L.n;
+            if (staged) {
+                for (int j = threadIdx.x; j < L.n; j += blockDim.x) sx[j] = x[j];
+                for (int i = threadIdx.x; i < L.m; i += blockDim.x) sy[i] = -(gk * y[i]);
+            }
+            __syncthreads();
             // element e = i n + j; (i, j) advance with e instead of a
-            // division per element (m n < 2^31 by the size limits)
+            // division per element (m n < 2^31 by the size limits).  Not
+            // OPTIMAL: zeros (x and y may be NaN; selected away, never
+            // multiplied by a zero weight)
             const int n = L.n, mn = L.m * n, step = (int)blockDim.x;
             const int di = step / n, dj = step - di * n;
             int i = (int)threadIdx.x / n, j = (int)threadIdx.x - i * n;
+            double* out = dA + L.a_off;
             for (int e = threadIdx.x; e < mn; e += step) {
-                dA[L.a_off + e] = ok ? -(gk * y[i]) * x[j] : 0.0;
+                out[e] = !ok ? 0.0 : staged ? sy[i] * sx[j] : -(gk * y[i]) * x[j];
                 i += di;
                 j += dj;
                 if (j >= n) {
@@ -417,6 +432,7 @@ __global__ void __launch_bounds__(256) backward_simplex_kernel(KParams P, const 
                     ++i;
                 }
             }
+            __syncthreads();  // the stage is reused by the next LP
         }
     }
 }
@@ -558,10 +574,11 @@ hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s) {
     hipLaunchKernelGGL(hyperbox_kernel, dim3(grid_for(max_items, 256, 1 << 16)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
-hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,
-                                   hipStream_t s) {
-    hipLaunchKernelGGL(backward_simplex_kernel, dim3(grid_for(P.count, 1, 1 << 16)), dim3(256), 0, s, P, g, dc,
-                       db, dA);
+hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA, int max_n,
+                                   int max_m, hipStream_t s) {
+    const int stage = max_n + max_m > 0 ? max_n + max_m : 1;  // at most 4095 + 2046 doubles
+    hipLaunchKernelGGL(backward_simplex_kernel, dim3(grid_for(P.count, 1, 1 << 16)), dim3(256),
+                       sizeof(double) * (size_t)stage, s, P, g, dc, db, dA, stage);
     return hipGetLastError();
 }
 // Adjoint of a shared-constraint solve (one A, b; objectives C, LP k's

@@ -48,8 +48,10 @@ hipError_t launch_scatter(int64_t count, int nbins, const int32_t* binid, const 
 hipError_t launch_order_bins(const KParams& P, int nbins, const int32_t* bin_count, const int32_t* bin_off,
                              const int32_t* list, int32_t* out, hipStream_t s);
 hipError_t launch_hyperbox(const KParams& P, int64_t max_items, hipStream_t s);
-hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA,
-                                   hipStream_t s);
+// max_n, max_m: the largest n and m of the batch's simplex LPs (the
+// workgroup stages x and the scaled y of one LP in LDS)
+hipError_t launch_backward_simplex(const KParams& P, const double* g, double* dc, double* db, double* dA, int max_n,
+                                   int max_m, hipStream_t s);
 hipError_t launch_backward_hyperbox(const KParams& P, int64_t max_items, const double* g, double* dc, double* dl,
                                     double* du, hipStream_t s);
 // Shared box: dl, du (length n) summed over the hyperbox LPs in a fixed

@@ -1693,7 +1693,8 @@ blp_error blp_backward(blp_handle h, const double* g, double* dc, double* db, do
     HIP_TRY(h, hipSetDevice(h->opt.device));
     HIP_TRY(h, begin_call(h, s));
     KParams P = h->last;
-    if (h->any_simplex && (dc || db || dA)) HIP_TRY(h, launch_backward_simplex(P, g, dc, db, dA, s));
+    if (h->any_simplex && (dc || db || dA))
+        HIP_TRY(h, launch_backward_simplex(P, g, dc, db, dA, h->plan.max_n, h->plan.max_m, s));
     if (h->any_box && (dc || dl || du)) {
         KParams Q = P;
         Q.bin = h->nreg + 1;

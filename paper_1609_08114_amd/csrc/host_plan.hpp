@@ -49,7 +49,7 @@ struct Plan {
     bool any_simplex = false, any_box = false;
     int64_t n_box = 0;
     int64_t tot_a = 0, tot_m = 0, tot_n = 0;  // extents of A, rows (b, sense, y), columns (c, l, u, x)
-    int max_m = 0, max_cols = 0;
+    int max_m = 0, max_n = 0, max_cols = 0;  // over the simplex LPs
     int64_t max_slot = 0;      // largest streaming tableau, doubles (16-row-aligned leading dimension)
     int64_t n_may_stream = 0;  // simplex LPs no register variant is sure to hold
     bool gm_deep = false;      // some LP fits no register tile even without artificial columns
@@ -81,7 +81,7 @@ inline int plan_batch(const PlanIn& in, Plan& p) {
     p.kind.assign(in.kind, in.kind + nmeta);
     p.any_simplex = p.any_box = p.gm_deep = false;
     p.n_box = p.tot_a = p.tot_m = p.tot_n = p.max_slot = p.n_may_stream = 0;
-    p.max_m = p.max_cols = p.box_n = 0;
+    p.max_m = p.max_n = p.max_cols = p.box_n = 0;
     // no register tile holds the LP even without artificial columns
     auto sure_stream = [&](int m, int n) {
         if (in.force == -2) return true;
@@ -112,6 +112,7 @@ inline int plan_batch(const PlanIn& in, Plan& p) {
                                  (long long)k, m, n, kMaxM, kMaxCols);
             p.any_simplex = true;
             p.max_m = std::max(p.max_m, m);
+            p.max_n = std::max(p.max_n, n);
             p.max_cols = std::max(p.max_cols, n + m + 1);
             p.max_slot = std::max<int64_t>(p.max_slot, (int64_t)((m + 2 + 15) / 16) * 16 * (n + m + 1));
             if (!sure_register(m, n)) ++p.n_may_stream;
