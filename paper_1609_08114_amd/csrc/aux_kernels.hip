@@ -455,7 +455,7 @@ __global__ void backward_hyperbox_kernel(KParams P, const double* g, double* dc,
     }
 }
 
-// ------------------------------------------------------------------ launchers
+// Route of a shared-constraint solve (aux_kernels.hpp: shared_route_of).
 __global__ void __launch_bounds__(256) shared_route_kernel(int m, int n, int64_t count, const double* b,
                                                             const int8_t* sense, const double* C, SharedRoute rt,
                                                             int32_t* route_len) {
@@ -503,6 +503,7 @@ __global__ void iota_kernel(int32_t* list, int64_t count) {
         list[q] = (int32_t)q;
 }
 
+// ------------------------------------------------------------------ launchers
 hipError_t launch_shared_route(int m, int n, int64_t count, const double* b, const int8_t* sense, const double* C,
                                const SharedRoute& rt, int32_t* route_len, hipStream_t s) {
     hipLaunchKernelGGL(shared_route_kernel, dim3(1), dim3(256), 0, s, m, n, count, b, sense, C, rt, route_len);
