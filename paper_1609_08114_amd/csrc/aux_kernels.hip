@@ -10,6 +10,8 @@
 //  - backward_simplex / backward_hyperbox: the adjoint of the optimum with
 //    respect to the data, from the primal and dual solutions.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 
 #include "aux_kernels.hpp"
 #include "blp_kernels.hpp"
@@ -41,33 +43,49 @@ __device__ __forceinline__ int art_count(const ArtLoads& a, int m, int i0, int l
     return __popcll(__ballot(ia < m && (a.sa != 0 ? -a.ba : a.ba) < 0.0)) +
            __popcll(__ballot(ib < m && (a.sb != 0 ? -a.bb : a.bb) < 0.0));
 }
-__device__ __forceinline__ int bin_of(const VariantTable& vt, const LpRef& L, int nart) {
+// The variant table spread over the lanes of a wave: lane v < nreg holds
+// variant v, loaded once per wave, so that choosing an LP's variant is one
+// compare per lane and one wave reduction instead of a loop of table loads.
+struct LaneVariant {
+    int rows, cols, type1, remap;
+    int64_t min_count;
+};
+__device__ __forceinline__ LaneVariant lane_variant(const VariantTable& vt, int lane) {
+    LaneVariant r{0, 0, 1, 0, INT64_MAX};  // lanes past the table never fit
+    if (lane < vt.nreg) {
+        r.rows = vt.rows[lane];
+        r.cols = vt.cols[lane];
+        r.type1 = vt.type1[lane];
+        r.remap = vt.remap[lane];
+        r.min_count = vt.min_count[lane];
+    }
+    return r;
+}
+// The LP's bin (all 64 lanes active, result wave-uniform): the forced
+// variant if it holds the LP; else the variant of smallest area that holds
+// it (the first of equal areas; the area times 32 plus the lane is the key of
+// a wave minimum), then the autotuner's remap of that variant.
+__device__ __forceinline__ int bin_of(const VariantTable& vt, const LaneVariant& lv, int lane, const LpRef& L,
+                                      int nart) {
     const int rows = L.m + 2, cols = L.n + nart + 1;
-    int bin = vt.nreg;  // streaming kernel
     // a variant for LPs without artificial rows under the largest-
     // coefficient rule takes only those
     const bool t1 = nart == 0 && vt.lpc;
-    const int64_t K = vt.count;
     if (vt.force >= 0) {
-        if (vt.force < vt.nreg && vt.rows[vt.force] >= rows && vt.cols[vt.force] >= cols &&
-            (t1 || !vt.type1[vt.force]))
-            bin = vt.force;
-    } else if (vt.force == -1) {
-        long best = -1;
-        for (int v = 0; v < vt.nreg; ++v) {
-            if (vt.rows[v] >= rows && vt.cols[v] >= cols && (t1 || !vt.type1[v]) && K >= vt.min_count[v]) {
-                const long area = (long)vt.rows[v] * vt.cols[v];
-                if (best < 0 || area < best) {
-                    best = area;
-                    bin = v;
-                }
-            }
-        }
-        if (bin < vt.nreg) {
-            const int r = vt.remap[bin];
-            if (r >= vt.nreg || t1 || !vt.type1[r]) bin = r;
-        }
+        const int f = vt.force;
+        if (f < vt.nreg && __builtin_amdgcn_readlane(lv.rows, f) >= rows &&
+            __builtin_amdgcn_readlane(lv.cols, f) >= cols && (t1 || !__builtin_amdgcn_readlane(lv.type1, f)))
+            return f;
+        return vt.nreg;
     }
+    if (vt.force != -1) return vt.nreg;  // streaming only
+    const bool fit = lane < vt.nreg && lv.rows >= rows && lv.cols >= cols && (t1 || !lv.type1) &&
+                     vt.count >= lv.min_count;
+    const int best = wave_min_i32(fit ? ((lv.rows * lv.cols) << 5) | lane : INT_MAX);
+    if (best == INT_MAX) return vt.nreg;
+    int bin = best & 31;
+    const int r = __builtin_amdgcn_readlane(lv.remap, bin);
+    if (r >= vt.nreg || t1 || !__builtin_amdgcn_readlane(lv.type1, r)) bin = r;
     return bin;
 }
 
@@ -78,6 +96,7 @@ __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable v
     for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const LaneVariant lv = lane_variant(vt, lane);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform: scalar branches below
     for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; k < P.count; k += 2 * nwaves) {
@@ -96,8 +115,8 @@ __global__ void __launch_bounds__(256) classify_kernel(KParams P, VariantTable v
         }
         for (int i0 = 128; s1 && i0 < L1.m; i0 += 128) n1 += art_count(art_load(P, L1, i0, lane), L1.m, i0, lane);
         for (int i0 = 128; s2 && i0 < L2.m; i0 += 128) n2 += art_count(art_load(P, L2, i0, lane), L2.m, i0, lane);
-        const int b1 = s1 ? bin_of(vt, L1, n1) : vt.nreg + 1;
-        const int b2 = k2 != k ? (s2 ? bin_of(vt, L2, n2) : vt.nreg + 1) : -1;
+        const int b1 = s1 ? bin_of(vt, lv, lane, L1, n1) : vt.nreg + 1;
+        const int b2 = k2 != k ? (s2 ? bin_of(vt, lv, lane, L2, n2) : vt.nreg + 1) : -1;
         if (lane == 0) {
             binid[k] = b1;
             atomicAdd(&hist[b1], 1);
@@ -523,7 +542,9 @@ hipError_t launch_reset(int32_t* counters, int n, hipStream_t s) {
     return hipGetLastError();
 }
 int classify_blocks(int64_t count) {
-    int64_t blocks = (count + 15) / 16;  // at least four LPs per wave
+    // one LP per wave to start with: the classification is a chain of
+    // dependent loads per LP, so more waves in flight finish it sooner
+    int64_t blocks = (count + 3) / 4;
     if (blocks > kClassifyMaxBlocks) blocks = kClassifyMaxBlocks;
     if (blocks < 1) blocks = 1;
     return (int)blocks;

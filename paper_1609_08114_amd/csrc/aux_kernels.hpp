@@ -8,7 +8,7 @@
 
 namespace blp {
 
-constexpr int kMaxVariants = 24;
+constexpr int kMaxVariants = 24;  // < 32: the classify kernel keys a variant by area * 32 + index
 // Widest uniform hyperbox served by the LDS-transposing kernel (LDS per wave:
 // 2 * 64 * (n + 1) doubles).
 constexpr int kBoxTileMaxN = 48;
@@ -32,7 +32,7 @@ hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);
 // bin], zeroed beforehand), so that the blocks' atomics spread over
 // kBinStripes lines; bin_offsets sums the copies into bin_count and writes
 // the exclusive prefix to bin_off.
-constexpr int kClassifyMaxBlocks = 2048;
+constexpr int kClassifyMaxBlocks = 8192;
 constexpr int kBinStripes = 64;
 constexpr int kStripeStride = 32;
 static_assert(kMaxVariants + 2 <= kStripeStride, "every bin of a stripe on its line");
